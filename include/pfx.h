@@ -1,0 +1,220 @@
+/*
+ * pfx — batched AC power flow on AMD MI355X (gfx950).
+ *
+ * C ABI of the device library.  Every entry point returns a pf_status; no C++
+ * exception crosses this boundary.  The text of the last failure on the
+ * calling thread is available from pf_last_error().
+ *
+ * Method (citations are to the paper "JAX-Based Batched AC Power Flow for GPU
+ * Acceleration and AI Ecosystem Integration"):
+ *   - transmission grids: Newton-Raphson on the polar state of eq. (1) with the
+ *     mismatch of eq. (2) and the update of eq. (3); each Newton system is
+ *     solved by restarted GMRES on Jacobian-vector products (Sec. II-A) with the
+ *     left preconditioner of eq. (7) applied by the forward block substitution
+ *     of eqs. (8)-(9), using (B' + eps I) and (B'' + eps I);
+ *   - radial three-phase feeders: the Z-bus fixed point of eq. (10) with wye
+ *     and delta constant-power loads (Sec. II-B).
+ *
+ * Conventions shared by all calls
+ *   - Per unit throughout; angles in radians, slack angle 0.
+ *   - "device" pointers are HIP device memory owned by the caller; "host"
+ *     pointers are read (copied) before the call returns.
+ *   - Per-scenario arrays are scenario-major: element (b, i) of a real array is
+ *     at [b * ld + i]; a complex array stores re, im interleaved, element
+ *     (b, i) at [2 * (b * ld + i)].  ld >= the row length (n_bus or n_node).
+ *   - Work is enqueued on the given stream and is asynchronous; outputs are
+ *     valid once the stream has been synchronised.  A null stream means the
+ *     default stream.
+ *   - Non-convergence of a scenario is not an error: it is reported through
+ *     that scenario's converged flag, iteration count and final mismatch.
+ */
+#ifndef PFX_H
+#define PFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pf_stream;   /* a hipStream_t */
+
+typedef enum pf_status {
+  PF_OK = 0,
+  PF_INVALID_ARG = 1,     /* a size, pointer or option is out of range */
+  PF_OUT_OF_MEMORY = 2,   /* a device allocation failed or the context budget is exceeded */
+  PF_HIP_ERROR = 3,       /* a HIP runtime call failed */
+  PF_SINGULAR_SETUP = 4,  /* a network matrix could not be factorised */
+  PF_NOT_ADMITTED = 5,    /* serving engine: no free slots for the request */
+  PF_BAD_HANDLE = 6       /* null or destroyed handle */
+} pf_status;
+
+typedef enum pf_precision {
+  PF_FP64 = 0,            /* every step in FP64 */
+  PF_MIXED = 1            /* FP32 inner solves / FP32 Zbus product; FP64 mismatch, test and update */
+} pf_precision;
+
+/* Solver options.  pf_opts_default() fills the defaults listed here. */
+typedef struct pf_opts {
+  int32_t precision;          /* pf_precision, default PF_FP64 */
+  double tol;                 /* converged when max |mismatch| <= tol (pu), default 1e-8 */
+  int32_t max_newton;         /* Newton updates at most, default 20 */
+  int32_t gmres_restart;      /* Krylov dimension per GMRES cycle, 1..64, default 30 */
+  int32_t gmres_max_restarts; /* GMRES cycles per Newton step at most, default 10 */
+  double gmres_rtol;          /* preconditioned residual reduction, default 1e-6 (0 = by precision:
+                                 1e-6 in PF_FP64, 1e-4 in PF_MIXED) */
+  double diverge;             /* a scenario whose mismatch exceeds this is abandoned, default 1e6 */
+  int32_t zbus_max_iter;      /* fixed-point updates at most, default 100 */
+  /* network set-up (read by the *_network_create calls only) */
+  double eps;                 /* diagonal regularisation of B' and B'' (Sec. II-A), default 1e-8 */
+  int32_t precond_block;      /* 0: exact (B'+eps I)^-1, (B''+eps I)^-1 (default);
+                                 k > 0: block-Jacobi over diagonal blocks of k buses */
+  int32_t factor_max_levels;  /* sparse elimination levels before the dense core, default 8 */
+  int32_t factor_max_core;    /* largest dense Schur core, default 384 */
+} pf_opts;
+
+void pf_opts_default(pf_opts* out);
+
+typedef struct pf_context pf_context;
+typedef struct pf_tx_network pf_tx_network;
+typedef struct pf_dist_network pf_dist_network;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the device
+ * workspace the context may hold (0 = no bound).  Errors: PF_INVALID_ARG,
+ * PF_HIP_ERROR. */
+pf_status pf_context_create(int32_t device, uint64_t hbm_budget_bytes, pf_context** out);
+/* Destroy a context and every network created in it.  Null is ignored. */
+void pf_context_destroy(pf_context* ctx);
+/* Message of the last failing call on this thread ("" if none).  The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* pf_last_error(void);
+/* Device bytes currently held by the context (networks and workspaces). */
+uint64_t pf_context_bytes(const pf_context* ctx);
+
+/* ---------------------------------------------------------- transmission */
+
+/* Build the bus admittance matrix of pi-model branches (Sec. II-A): branch k
+ * from f[k] to t[k] with series impedance r[k] + j x[k] and total charging
+ * b[k] adds y_s + j b/2 to both diagonal entries and -y_s to both
+ * off-diagonal ones.  All pointers are host.  Output CSR (host, caller
+ * allocated): row_ptr[n_bus + 1], col_idx[cap], y_re[cap], y_im[cap] with
+ * columns sorted and duplicates summed; *nnz_out receives the count.
+ * Errors: PF_INVALID_ARG (index out of range, zero impedance, cap too small:
+ * then *nnz_out still receives the required count). */
+pf_status pf_tx_ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_t* f,
+                                   const int32_t* t, const double* r, const double* x,
+                                   const double* b, int32_t cap, int32_t* row_ptr,
+                                   int32_t* col_idx, double* y_re, double* y_im, int32_t* nnz_out);
+
+/* Register a transmission network (Sec. II-A).  Host inputs, copied:
+ *   Ybus as CSR (row_ptr[n_bus+1], col_idx[nnz], y_re[nnz], y_im[nnz]);
+ *   bus_type[n_bus]: 0 = PQ, 1 = PV, 2 = slack, exactly one slack.
+ *   Optional branch list (n_branch may be 0; needed only by the branch-loss
+ *   calls): from/to buses, series impedance r + j x and total charging b.
+ * The index sets are Theta = PV u PQ and Q = PQ (Sec. II-A); B' and B'' are
+ * -Im(Ybus) on Theta x Theta and Q x Q, G = -Re(Ybus) on Q x Theta (eq. (7)).
+ * Their regularised inverses are factorised here, once (Sec. II-A: the
+ * inverses are precomputed).  setup_opts may be null (defaults).
+ * Errors: PF_INVALID_ARG, PF_SINGULAR_SETUP, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_tx_network_create(pf_context* ctx, int32_t n_bus, int32_t nnz, const int32_t* row_ptr,
+                               const int32_t* col_idx, const double* y_re, const double* y_im,
+                               const int8_t* bus_type, int32_t n_branch, const int32_t* br_f,
+                               const int32_t* br_t, const double* br_r, const double* br_x,
+                               const double* br_b, const pf_opts* setup_opts, pf_tx_network** out);
+void pf_tx_network_destroy(pf_tx_network* net);
+/* Sizes: n_bus, |Theta|, |Q|, nnz(Ybus), sparse factor nonzeros and dense core
+ * sizes of the B' and B'' inverses (any pointer may be null). */
+pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* n_theta,
+                             int32_t* n_q, int32_t* nnz, int32_t* factor_nnz, int32_t* core_bp,
+                             int32_t* core_bpp);
+
+/* Batched Newton-Raphson (eqs. (1)-(3)) from a flat start for `batch`
+ * scenarios.  Device inputs [batch][ld]: p_inj, q_inj (scheduled injections,
+ * generation minus load) and vm_set (|V| set-points at PV buses and the slack;
+ * read only there).  Device outputs: v_out complex [batch][ld] (all buses),
+ * newton_iters[batch] (updates taken), gmres_iters[batch] (Arnoldi steps over
+ * all Newton steps), converged[batch] (1 when max |F| <= tol),
+ * final_mismatch[batch] (max |F| at v_out).  Optional outputs may be null:
+ * gmres_iters, final_mismatch.  batch may be 0 (no work).
+ * Errors: PF_INVALID_ARG (ld < n_bus, batch < 0, bad options),
+ * PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_tx_solve(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
+                      const double* p_inj, const double* q_inj, const double* vm_set,
+                      double* v_out, int32_t* newton_iters, int32_t* gmres_iters,
+                      uint8_t* converged, double* final_mismatch, pf_stream stream);
+
+/* Branch loss L_b = sum over branches of |I_f|^2 with the from-end current
+ * I_f = (y_s + j b/2) V_f - y_s V_t, for voltages v (device complex
+ * [batch][ld]).  Outputs (device): loss[batch] and, if dl_dv is not null, the
+ * gradient in torch's convention dL/dRe V + j dL/dIm V, complex [batch][ld].
+ * Needs the branch list given at network creation.
+ * Errors: PF_INVALID_ARG, PF_HIP_ERROR. */
+pf_status pf_tx_branch_loss(pf_tx_network* net, int32_t batch, int64_t ld, const double* v,
+                            double* loss, double* dl_dv, pf_stream stream);
+
+/* Adjoint of the solved state: for converged voltages v (device complex
+ * [batch][ld]) and an upstream gradient dl_dv (device complex [batch][ld],
+ * torch convention), solve J^T lambda = dL/dx by restarted GMRES on
+ * transposed Jacobian-vector products with the transposed preconditioner of
+ * eq. (7), and return dL/dP = lambda_P on Theta buses and dL/dQ = lambda_Q on
+ * PQ buses (device [batch][ld], zero elsewhere).  Always FP64.
+ * gmres_iters and converged (device, [batch]) may be null.
+ * Errors: PF_INVALID_ARG, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_tx_adjoint(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
+                        const double* v, const double* dl_dv, double* grad_p, double* grad_q,
+                        int32_t* gmres_iters, uint8_t* converged, pf_stream stream);
+
+/* ---------------------------------------------------------- distribution */
+
+/* Build the three-phase admittance matrix of a radial feeder (Sec. II-B):
+ * segment k joins bus seg_from[k] to seg_to[k] with 3x3 series impedance
+ * z[k] (row-major, complex interleaved, 18 doubles per segment); phase node
+ * 3*bus + phase.  Each segment adds inv(z) to both diagonal 3x3 blocks and
+ * -inv(z) to both off-diagonal blocks.  Output CSR as for the transmission
+ * builder over 3*n_bus nodes.  Errors: PF_INVALID_ARG, PF_SINGULAR_SETUP. */
+pf_status pf_dist_ybus_from_segments(int32_t n_bus, int32_t n_seg, const int32_t* seg_from,
+                                     const int32_t* seg_to, const double* z, int32_t cap,
+                                     int32_t* row_ptr, int32_t* col_idx, double* y_re, double* y_im,
+                                     int32_t* nnz_out);
+
+/* Register a feeder.  Host inputs, copied: three-phase Ybus CSR over n_node
+ * phase nodes; slack_nodes[3] with voltages v_slack (re/im interleaved, 6
+ * doubles); wye_node[n_wye] (nodes that may carry a wye load);
+ * delta_nodes[n_delta][3] (phase nodes a, b, c of each delta-loaded bus).
+ * Computes the reduced impedance Z = inv(Y_NN) over the non-slack nodes N and
+ * the no-load voltage v0 = -Z Y_NS v_S (Sec. II-B, eq. (10)) in FP64, keeps Z
+ * in FP64 and FP32 on the device.  setup_opts may be null.
+ * Errors: PF_INVALID_ARG, PF_SINGULAR_SETUP, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_dist_network_create(pf_context* ctx, int32_t n_node, int32_t nnz, const int32_t* row_ptr,
+                                 const int32_t* col_idx, const double* y_re, const double* y_im,
+                                 const int32_t* slack_nodes, const double* v_slack, int32_t n_wye,
+                                 const int32_t* wye_node, int32_t n_delta, const int32_t* delta_nodes,
+                                 const pf_opts* setup_opts, pf_dist_network** out);
+void pf_dist_network_destroy(pf_dist_network* net);
+pf_status pf_dist_network_info(const pf_dist_network* net, int32_t* n_node, int32_t* n_free,
+                               int32_t* n_wye, int32_t* n_delta);
+
+/* Batched Z-bus fixed point (eq. (10)) from v = v0.  Device inputs complex
+ * [batch][ld] over all phase nodes, consumption convention: s_wye (wye load on
+ * each node; read at wye nodes only) and s_delta (for a delta bus with nodes
+ * a, b, c: the ab, bc, ca branch loads at a, b, c; read at delta nodes only).
+ * The iteration is run in residual form v <- v + Z r, r = i(v) - (Y_NN v +
+ * Y_NS v_S), which equals Z i(v) + v0 exactly; a scenario is converged when
+ * max |v * conj(r)| <= tol.  Device outputs: v_out complex [batch][ld] (all
+ * nodes, slack included), iters[batch], converged[batch], final_mismatch
+ * [batch] (may be null), sum_abs_change[batch] (the change of sum |v| over the
+ * last update, the paper's stop quantity; may be null).
+ * Errors: PF_INVALID_ARG, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_dist_solve(pf_dist_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
+                        const double* s_wye, const double* s_delta, double* v_out, int32_t* iters,
+                        uint8_t* converged, double* final_mismatch, double* sum_abs_change,
+                        pf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFX_H */

@@ -136,19 +136,19 @@ def nr_solve(Y, bus_type, p, q, vm_set, tol=1e-8, max_iter=20, diverge=1e6, V0=N
 def nr_solve_batch(grid, batch, tol=1e-8, max_iter=20, columns=None):
     """Solve the scenarios of a ``workloads.transmission`` batch one by one.
 
-    Returns (V [n, nb] complex, iters [nb], converged [nb], mismatch [nb]) for
-    the requested ``columns`` (default: all).
+    Returns (V [nb, n] complex, iters [nb], converged [nb], mismatch [nb]) for
+    the requested scenarios ``columns`` (default: all).
     """
     Y = ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
     cols = np.arange(batch.batch) if columns is None else np.asarray(columns)
-    V = np.zeros((grid.n_bus, cols.shape[0]), dtype=np.complex128)
+    V = np.zeros((cols.shape[0], grid.n_bus), dtype=np.complex128)
     it = np.zeros(cols.shape[0], dtype=np.int32)
     ok = np.zeros(cols.shape[0], dtype=bool)
     mm = np.zeros(cols.shape[0])
     for j, c in enumerate(cols):
-        res = nr_solve(Y, grid.bus_type, batch.p_inj[:, c], batch.q_inj[:, c], batch.vm_set[:, c],
+        res = nr_solve(Y, grid.bus_type, batch.p_inj[c], batch.q_inj[c], batch.vm_set[c],
                        tol=tol, max_iter=max_iter)
-        V[:, j] = res.V
+        V[j] = res.V
         it[j] = res.iters
         ok[j] = res.converged
         mm[j] = res.mismatch

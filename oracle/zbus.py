@@ -92,7 +92,7 @@ def _nonslack_delta(feeder, N):
 
 @dataclass
 class ZbusResult:
-    v: np.ndarray              # complex128 [n_node, B] all phase nodes incl. the slack
+    v: np.ndarray              # complex128 [B, n_node] all phase nodes incl. the slack
     iters: np.ndarray          # int32 [B] fixed-point updates until the stop rule
     converged: np.ndarray      # bool [B]: voltage change reached tol_v
     mismatch: np.ndarray       # float64 [B] max |v * conj(r)| over non-slack nodes
@@ -100,7 +100,9 @@ class ZbusResult:
 
 
 def residual(feeder, v_all, s_wye, s_delta):
-    """r = i(v) - (Y_NN v_N + Y_NS v_S) over the non-slack nodes, and the mismatch v * conj(r)."""
+    """r = i(v) - (Y_NN v_N + Y_NS v_S) over the non-slack nodes, and the mismatch v * conj(r).
+
+    Arguments and results are node-major ([n_node, B] in, [nN, B] out)."""
     YNN, YNS, N = split(feeder)
     dN = _nonslack_delta(feeder, N)
     vN = v_all[N]
@@ -112,8 +114,8 @@ def zbus_solve(feeder, batch, tol_v=1e-13, max_iter=200):
     """Run v <- Z i(v) + v0 from v0 for every scenario of the batch (eq. (10))."""
     Z, v0, N = zbus(feeder)
     dN = _nonslack_delta(feeder, N)
-    sw = batch.s_wye[N]
-    sd = batch.s_delta[N]
+    sw = batch.s_wye.T[N]
+    sd = batch.s_delta.T[N]
     B = batch.batch
     v = np.repeat(v0[:, None], B, axis=1)
     iters = np.full(B, max_iter, dtype=np.int32)
@@ -134,7 +136,7 @@ def zbus_solve(feeder, batch, tol_v=1e-13, max_iter=200):
     v_all = np.zeros((feeder.n_node, B), dtype=np.complex128)
     v_all[SLACK_NODES] = feeder.v_slack[:, None]
     v_all[N] = v
-    _, dS = residual(feeder, v_all, batch.s_wye, batch.s_delta)
+    _, dS = residual(feeder, v_all, batch.s_wye.T, batch.s_delta.T)
     mm = np.max(np.abs(dS), axis=0)
-    return ZbusResult(v=v_all, iters=iters, converged=done, mismatch=mm,
+    return ZbusResult(v=v_all.T.copy(), iters=iters, converged=done, mismatch=mm,
                       sum_abs_change=last_sum_change)

@@ -1,0 +1,87 @@
+// Three-phase radial feeder for the Z-bus fixed point (Sec. II-B, eq. (10)).
+//
+// Free nodes (all phase nodes except the three slack phases) are numbered
+// 0..nN-1 in the caller's order.  Per-scenario state is scenario-major with a
+// padded row of Kp reals: node i's complex value is at [2i], [2i+1].  The
+// product delta = Z r is a real GEMM D = R W over those rows, with W the
+// real-block form of Z:
+//   W[2l][2i] = Re Z[i][l],  W[2l+1][2i] = -Im Z[i][l],
+//   W[2l][2i+1] = Im Z[i][l], W[2l+1][2i+1] = Re Z[i][l],
+// zero-padded to Kp x Np (Kp = 2 nN rounded up to the GEMM's K step, Np to
+// its N tile).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace pfx {
+
+struct DistDev {
+  int nN, Kp, Np;
+  const int* y_ptr;        // Y_NN CSR over free nodes
+  const int* y_col;
+  const double* y_re;
+  const double* y_im;
+  const double* c;         // Y_NS v_S, complex interleaved [nN]
+  const double* v0;        // no-load voltage, complex interleaved [nN]
+  const int* free2ext;     // free node -> caller's node index
+  const uint8_t* wye;      // [nN] 1 if the node may carry a wye load
+  const int* d_next;       // [nN] delta partner: next phase of the bus (-1 if not delta)
+  const int* d_prev;       // [nN] previous phase of the bus
+};
+
+struct DistNetwork {
+  Context* ctx = nullptr;
+  int n_node = 0, nN = 0, nnz = 0, Kp = 0, Np = 0, n_wye = 0, n_delta = 0;
+  int slack[3] = {0, 1, 2};
+  double v_slack[6] = {0, 0, 0, 0, 0, 0};
+  std::vector<int> free2ext;
+  DeviceBuffer y_ptr, y_col, y_re, y_im, c, v0, free2ext_d, wye, d_next, d_prev;
+  DeviceBuffer W64, W32;   // Kp x Np real-block Z (Np = 2 nN rounded up to the N tile)
+  DeviceBuffer slack_d;    // 3 slack node indices
+  DeviceBuffer vslack_d;   // 6 doubles
+  // workspaces (grow-only); calls on one network must not overlap
+  DeviceBuffer ws_v, ws_r, ws_s, ws_act, ws_cnt;
+  int32_t* count_host = nullptr;   // pinned readback of the active counts
+  int count_host_len = 0;
+  ~DistNetwork();
+  DistDev view() const;
+};
+
+DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_t* row_ptr,
+                                 const int32_t* col_idx, const double* y_re, const double* y_im,
+                                 const int32_t* slack_nodes, const double* v_slack, int n_wye,
+                                 const int32_t* wye_node, int n_delta, const int32_t* delta_nodes,
+                                 const pf_opts& setup);
+
+// GEMM tile sizes shared by the host sizing and the kernels.
+constexpr int ZB_BM = 128;   // scenarios per tile
+constexpr int ZB_BN = 128;   // output reals per tile
+constexpr int ZB_BK = 16;    // K step
+
+struct ZbusLaunch {
+  int batch;
+  int64_t ld;
+  const double* s_wye;
+  const double* s_delta;
+  double* v_out;
+  int32_t* iters;
+  uint8_t* converged;
+  double* final_mismatch;
+  double* sum_abs_change;
+  double tol;
+  int max_iter;
+  // workspace
+  double* v;          // [rows][Kp] FP64 state
+  void* r;            // [rows][Kp] residual in the GEMM's type (rows = batch rounded up to ZB_BM)
+  double* st;         // [batch][3]: mismatch, sum |v| at the last residual, change of sum |v|
+  int32_t* active;    // [rows] 1 while the scenario still iterates
+  int32_t* count;     // [max_iter + 1] scenarios still active at each iteration
+};
+
+// Runs the whole fixed point on `stream` (host loop over iterations).
+void run_zbus(DistNetwork& net, bool mixed, const ZbusLaunch& a, hipStream_t s);
+
+}  // namespace pfx

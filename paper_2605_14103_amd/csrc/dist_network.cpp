@@ -1,0 +1,221 @@
+// Feeder registration: slack/non-slack split, reduced impedance matrix
+// Z = inv(Y_NN) and no-load voltage v0 = -Z Y_NS v_S (Sec. II-B, eq. (10)).
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <string>
+
+#include "dist.hpp"
+
+namespace pfx {
+
+namespace {
+
+using cplx = std::complex<double>;
+
+// In-place inverse of a dense complex matrix (row-major n x n) by LU with
+// partial pivoting.  Throws PF_SINGULAR_SETUP on a zero pivot.
+void invert_dense(std::vector<cplx>& A, int n) {
+  std::vector<int> piv(n);
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    double best = std::abs(A[(size_t)k * n + k]);
+    for (int i = k + 1; i < n; ++i) {
+      double v = std::abs(A[(size_t)i * n + k]);
+      if (v > best) {
+        best = v;
+        p = i;
+      }
+    }
+    if (!(best > 0)) fail(PF_SINGULAR_SETUP, "Y_NN is singular at column " + std::to_string(k));
+    piv[k] = p;
+    if (p != k)
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+    const cplx inv = 1.0 / A[(size_t)k * n + k];
+    for (int i = k + 1; i < n; ++i) {
+      cplx l = A[(size_t)i * n + k] * inv;
+      A[(size_t)i * n + k] = l;
+      if (l == cplx(0.0))
+        continue;
+      cplx* ri = &A[(size_t)i * n];
+      const cplx* rk = &A[(size_t)k * n];
+      for (int j = k + 1; j < n; ++j) ri[j] -= l * rk[j];
+    }
+  }
+  // Solve for the inverse column by column: A = P^T L U.
+  std::vector<cplx> X((size_t)n * n, cplx(0.0));
+  std::vector<cplx> col(n);
+  for (int c = 0; c < n; ++c) {
+    std::fill(col.begin(), col.end(), cplx(0.0));
+    col[c] = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (piv[k] != k) std::swap(col[k], col[piv[k]]);
+    for (int i = 0; i < n; ++i) {
+      cplx s = col[i];
+      const cplx* ri = &A[(size_t)i * n];
+      for (int j = 0; j < i; ++j) s -= ri[j] * col[j];
+      col[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      cplx s = col[i];
+      const cplx* ri = &A[(size_t)i * n];
+      for (int j = i + 1; j < n; ++j) s -= ri[j] * col[j];
+      col[i] = s / ri[i];
+    }
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + c] = col[i];
+  }
+  A.swap(X);
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+DistDev DistNetwork::view() const {
+  DistDev d;
+  d.nN = nN;
+  d.Kp = Kp;
+  d.Np = Np;
+  d.y_ptr = y_ptr.as<int>();
+  d.y_col = y_col.as<int>();
+  d.y_re = y_re.as<double>();
+  d.y_im = y_im.as<double>();
+  d.c = c.as<double>();
+  d.v0 = v0.as<double>();
+  d.free2ext = free2ext_d.as<int>();
+  d.wye = wye.as<uint8_t>();
+  d.d_next = d_next.as<int>();
+  d.d_prev = d_prev.as<int>();
+  return d;
+}
+
+DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_t* row_ptr,
+                                 const int32_t* col_idx, const double* y_re, const double* y_im,
+                                 const int32_t* slack_nodes, const double* v_slack, int n_wye,
+                                 const int32_t* wye_node, int n_delta, const int32_t* delta_nodes,
+                                 const pf_opts& setup) {
+  (void)setup;
+  require(n_node >= 4, "a feeder needs the three slack phases and at least one free node");
+  require(row_ptr && col_idx && y_re && y_im && slack_nodes && v_slack, "null argument");
+  require(row_ptr[0] == 0 && row_ptr[n_node] == nnz && nnz >= 0, "bad row_ptr");
+  require(n_wye >= 0 && n_delta >= 0, "bad load counts");
+  if (n_wye > 0) require(wye_node != nullptr, "null wye_node");
+  if (n_delta > 0) require(delta_nodes != nullptr, "null delta_nodes");
+  auto net = std::make_unique<DistNetwork>();
+  net->ctx = ctx;
+  net->n_node = n_node;
+  std::vector<int> ext2free(n_node, 0);
+  for (int s = 0; s < 3; ++s) {
+    require(slack_nodes[s] >= 0 && slack_nodes[s] < n_node, "slack node out of range");
+    net->slack[s] = slack_nodes[s];
+    ext2free[slack_nodes[s]] = -1;
+  }
+  require(slack_nodes[0] != slack_nodes[1] && slack_nodes[1] != slack_nodes[2] &&
+              slack_nodes[0] != slack_nodes[2],
+          "slack nodes must be distinct");
+  for (int q = 0; q < 6; ++q) net->v_slack[q] = v_slack[q];
+  for (int i = 0; i < n_node; ++i)
+    if (ext2free[i] == 0) {
+      ext2free[i] = (int)net->free2ext.size();
+      net->free2ext.push_back(i);
+    }
+  const int nN = (int)net->free2ext.size();
+  net->nN = nN;
+  net->Kp = round_up(2 * nN, ZB_BK);
+  net->Np = round_up(2 * nN, ZB_BN);
+
+  // Y_NN (CSR over free nodes) and c = Y_NS v_S.
+  std::vector<int> yp(nN + 1, 0), yc;
+  std::vector<double> yr, yi, cc(2 * (size_t)nN, 0.0);
+  std::vector<cplx> Yd((size_t)nN * nN, cplx(0.0));
+  for (int fi = 0; fi < nN; ++fi) {
+    const int e = net->free2ext[fi];
+    require(row_ptr[e + 1] >= row_ptr[e], "row_ptr must be non-decreasing");
+    std::map<int, cplx> row;
+    cplx acc(0.0);
+    for (int p = row_ptr[e]; p < row_ptr[e + 1]; ++p) {
+      const int j = col_idx[p];
+      require(j >= 0 && j < n_node, "column index out of range");
+      const cplx y(y_re[p], y_im[p]);
+      if (ext2free[j] >= 0) {
+        row[ext2free[j]] += y;
+      } else {
+        int s = j == slack_nodes[0] ? 0 : (j == slack_nodes[1] ? 1 : 2);
+        acc += y * cplx(v_slack[2 * s], v_slack[2 * s + 1]);
+      }
+    }
+    for (auto& [j, y] : row) {
+      yc.push_back(j);
+      yr.push_back(y.real());
+      yi.push_back(y.imag());
+      Yd[(size_t)fi * nN + j] = y;
+    }
+    yp[fi + 1] = (int)yc.size();
+    cc[2 * fi] = acc.real();
+    cc[2 * fi + 1] = acc.imag();
+  }
+  net->nnz = (int)yc.size();
+
+  invert_dense(Yd, nN);  // Yd now holds Z
+  std::vector<double> v0(2 * (size_t)nN);
+  for (int i = 0; i < nN; ++i) {
+    cplx s(0.0);
+    for (int l = 0; l < nN; ++l) s += Yd[(size_t)i * nN + l] * cplx(cc[2 * l], cc[2 * l + 1]);
+    v0[2 * i] = -s.real();
+    v0[2 * i + 1] = -s.imag();
+  }
+  const int Kp = net->Kp, Np = net->Np;
+  std::vector<double> W((size_t)Kp * Np, 0.0);
+  for (int i = 0; i < nN; ++i)
+    for (int l = 0; l < nN; ++l) {
+      const cplx z = Yd[(size_t)i * nN + l];
+      W[(size_t)(2 * l) * Np + 2 * i] = z.real();
+      W[(size_t)(2 * l + 1) * Np + 2 * i] = -z.imag();
+      W[(size_t)(2 * l) * Np + 2 * i + 1] = z.imag();
+      W[(size_t)(2 * l + 1) * Np + 2 * i + 1] = z.real();
+    }
+
+  // Load tables.
+  std::vector<uint8_t> wye(nN, 0);
+  for (int q = 0; q < n_wye; ++q) {
+    const int e = wye_node[q];
+    require(e >= 0 && e < n_node && ext2free[e] >= 0, "wye load node must be a free node");
+    wye[ext2free[e]] = 1;
+  }
+  std::vector<int> dn(nN, -1), dpv(nN, -1);
+  for (int q = 0; q < n_delta; ++q) {
+    int f[3];
+    for (int p = 0; p < 3; ++p) {
+      const int e = delta_nodes[3 * q + p];
+      require(e >= 0 && e < n_node && ext2free[e] >= 0, "delta load node must be a free node");
+      f[p] = ext2free[e];
+      require(dn[f[p]] < 0, "a node belongs to two delta loads");
+    }
+    require(f[0] != f[1] && f[1] != f[2] && f[0] != f[2], "delta nodes must be distinct");
+    for (int p = 0; p < 3; ++p) {
+      dn[f[p]] = f[(p + 1) % 3];
+      dpv[f[p]] = f[(p + 2) % 3];
+    }
+  }
+  net->n_wye = n_wye;
+  net->n_delta = n_delta;
+
+  net->y_ptr = upload(ctx, yp);
+  net->y_col = upload(ctx, yc);
+  net->y_re = upload(ctx, yr);
+  net->y_im = upload(ctx, yi);
+  net->c = upload(ctx, cc);
+  net->v0 = upload(ctx, v0);
+  net->free2ext_d = upload(ctx, net->free2ext);
+  net->wye = upload(ctx, wye);
+  net->d_next = upload(ctx, dn);
+  net->d_prev = upload(ctx, dpv);
+  net->W64 = upload(ctx, W);
+  net->W32 = upload(ctx, std::vector<float>(W.begin(), W.end()));
+  net->slack_d = upload(ctx, std::vector<int>(net->slack, net->slack + 3));
+  net->vslack_d = upload(ctx, std::vector<double>(net->v_slack, net->v_slack + 6));
+  return net.release();
+}
+
+}  // namespace pfx

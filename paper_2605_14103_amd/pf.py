@@ -1,0 +1,260 @@
+"""Python binding of the device library: argument marshalling only.
+
+Every step of the solvers runs in the library's HIP kernels; this module turns
+torch tensors (device memory) and numpy arrays (host network data) into the
+pointers and sizes of the C ABI in include/pfx.h, and torch's current HIP
+stream into the stream argument.
+
+Layout: per-scenario tensors are scenario-major, shape (batch, n) with unit
+stride along n; the row stride is passed as ``ld``.  Complex tensors are
+complex128 (re, im interleaved, as the ABI expects).
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import byref, c_int32, c_void_p
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream) -> c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return c_void_p(stream.cuda_stream)
+
+
+def _dptr(t: torch.Tensor | None) -> c_void_p | None:
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def _hptr(a: np.ndarray) -> c_void_p:
+    return c_void_p(a.ctypes.data)
+
+
+def _rows(t: torch.Tensor, n: int, dtype: torch.dtype, name: str) -> int:
+    """Check a (batch, n) device tensor and return its row stride in elements."""
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != 2 or t.shape[1] != n:
+        raise ValueError(f"{name} must have shape (batch, {n}), got {tuple(t.shape)}")
+    if t.shape[0] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit stride along its second dimension")
+    return int(t.stride(0)) if t.shape[0] > 1 else n
+
+
+def _ld(*pairs) -> int:
+    lds = {_rows(t, n, dt, name) for t, n, dt, name in pairs}
+    if len(lds) != 1:
+        raise ValueError("all per-scenario tensors of one call must share a row stride")
+    return lds.pop()
+
+
+class Context:
+    """A device context (one per GPU); owns the networks created in it."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = int(device)
+        h = c_void_p()
+        L.call("pf_context_create", self.device, int(hbm_budget_bytes), byref(h))
+        self.h = h
+
+    def bytes(self) -> int:
+        return int(L.lib().pf_context_bytes(self.h))
+
+    def close(self) -> None:
+        if self.h:
+            L.lib().pf_context_destroy(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _setup_opts(setup: dict) -> L.PfOpts:
+    return L.opts(**setup)
+
+
+@dataclass
+class TxResult:
+    v: torch.Tensor              # complex128 (batch, n_bus)
+    newton_iters: torch.Tensor   # int32 (batch,)
+    gmres_iters: torch.Tensor    # int32 (batch,)
+    converged: torch.Tensor      # uint8 (batch,)
+    mismatch: torch.Tensor       # float64 (batch,)
+
+
+class TxNetwork:
+    """A registered transmission grid (Newton-Raphson, Sec. II-A)."""
+
+    def __init__(self, ctx: Context, n_bus: int, bus_type, f, t, r, x, b, **setup):
+        self.ctx = ctx
+        self.n_bus = int(n_bus)
+        f = np.ascontiguousarray(f, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int32)
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        bt = np.ascontiguousarray(bus_type, dtype=np.int8)
+        nbr = int(f.shape[0])
+        cap = self.n_bus + 2 * nbr
+        ptr = np.zeros(self.n_bus + 1, dtype=np.int32)
+        col = np.zeros(cap, dtype=np.int32)
+        yre = np.zeros(cap)
+        yim = np.zeros(cap)
+        nnz = c_int32()
+        L.call("pf_tx_ybus_from_branches", self.n_bus, nbr, _hptr(f), _hptr(t), _hptr(r), _hptr(x), _hptr(b),
+               cap, _hptr(ptr), _hptr(col), _hptr(yre), _hptr(yim), byref(nnz))
+        h = c_void_p()
+        so = _setup_opts(setup)
+        L.call("pf_tx_network_create", ctx.h, self.n_bus, nnz.value, _hptr(ptr), _hptr(col), _hptr(yre),
+               _hptr(yim), _hptr(bt), nbr, _hptr(f), _hptr(t), _hptr(r), _hptr(x), _hptr(b), byref(so), byref(h))
+        self.h = h
+        self.info = self._info()
+
+    @classmethod
+    def from_grid(cls, ctx: Context, grid, **setup) -> "TxNetwork":
+        """From a ``workloads.transmission.TxGrid``."""
+        return cls(ctx, grid.n_bus, grid.bus_type, grid.f, grid.t, grid.r, grid.x, grid.b, **setup)
+
+    def _info(self) -> dict:
+        vals = [c_int32() for _ in range(7)]
+        L.call("pf_tx_network_info", self.h, *[byref(v) for v in vals])
+        keys = ["n_bus", "n_theta", "n_q", "nnz", "factor_nnz", "core_bp", "core_bpp"]
+        return {k: v.value for k, v in zip(keys, vals)}
+
+    def close(self) -> None:
+        if self.h:
+            L.lib().pf_tx_network_destroy(self.h)
+            self.h = c_void_p()
+
+    def solve(self, p_inj: torch.Tensor, q_inj: torch.Tensor, vm_set: torch.Tensor, *, stream=None,
+              out: TxResult | None = None, **opts) -> TxResult:
+        """Batched Newton-Raphson from a flat start; see pf_tx_solve."""
+        n = self.n_bus
+        ld = _ld((p_inj, n, torch.float64, "p_inj"), (q_inj, n, torch.float64, "q_inj"),
+                 (vm_set, n, torch.float64, "vm_set"))
+        B = int(p_inj.shape[0])
+        dev = p_inj.device
+        if out is None:
+            out = TxResult(v=torch.empty((B, n), dtype=torch.complex128, device=dev),
+                           newton_iters=torch.empty(B, dtype=torch.int32, device=dev),
+                           gmres_iters=torch.empty(B, dtype=torch.int32, device=dev),
+                           converged=torch.empty(B, dtype=torch.uint8, device=dev),
+                           mismatch=torch.empty(B, dtype=torch.float64, device=dev))
+        if B > 1 and out.v.stride(0) != ld:
+            raise ValueError("output rows must use the input row stride")
+        o = L.opts(**opts)
+        L.call("pf_tx_solve", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
+               _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters), _dptr(out.converged),
+               _dptr(out.mismatch), _stream(stream))
+        return out
+
+    def branch_loss(self, v: torch.Tensor, *, grad: bool = True, stream=None):
+        """(loss (batch,), dL/dV in torch's convention or None); see pf_tx_branch_loss."""
+        ld = _ld((v, self.n_bus, torch.complex128, "v"))
+        B = int(v.shape[0])
+        loss = torch.empty(B, dtype=torch.float64, device=v.device)
+        g = torch.empty_like(v) if grad else None
+        L.call("pf_tx_branch_loss", self.h, B, ld, _dptr(v), _dptr(loss), _dptr(g), _stream(stream))
+        return loss, g
+
+    def adjoint(self, v: torch.Tensor, dl_dv: torch.Tensor, *, stream=None, **opts):
+        """(grad_p, grad_q, gmres_iters, converged); see pf_tx_adjoint."""
+        n = self.n_bus
+        ld = _ld((v, n, torch.complex128, "v"), (dl_dv, n, torch.complex128, "dl_dv"))
+        B = int(v.shape[0])
+        gp = torch.empty((B, n), dtype=torch.float64, device=v.device)
+        gq = torch.empty((B, n), dtype=torch.float64, device=v.device)
+        if B > 1 and gp.stride(0) != ld:
+            gp = torch.empty_strided((B, n), (ld, 1), dtype=torch.float64, device=v.device)
+            gq = torch.empty_strided((B, n), (ld, 1), dtype=torch.float64, device=v.device)
+        its = torch.empty(B, dtype=torch.int32, device=v.device)
+        ok = torch.empty(B, dtype=torch.uint8, device=v.device)
+        o = L.opts(**opts)
+        L.call("pf_tx_adjoint", self.h, byref(o), B, ld, _dptr(v), _dptr(dl_dv), _dptr(gp), _dptr(gq),
+               _dptr(its), _dptr(ok), _stream(stream))
+        return gp, gq, its, ok
+
+
+@dataclass
+class DistResult:
+    v: torch.Tensor               # complex128 (batch, n_node)
+    iters: torch.Tensor           # int32 (batch,)
+    converged: torch.Tensor       # uint8 (batch,)
+    mismatch: torch.Tensor        # float64 (batch,)
+    sum_abs_change: torch.Tensor  # float64 (batch,)
+
+
+class DistNetwork:
+    """A registered three-phase radial feeder (Z-bus fixed point, Sec. II-B)."""
+
+    def __init__(self, ctx: Context, n_bus: int, seg_from, seg_to, z_seg, slack_nodes, v_slack,
+                 wye_nodes, delta_nodes, **setup):
+        self.ctx = ctx
+        self.n_node = 3 * int(n_bus)
+        sf = np.ascontiguousarray(seg_from, dtype=np.int32)
+        st = np.ascontiguousarray(seg_to, dtype=np.int32)
+        z = np.ascontiguousarray(np.asarray(z_seg, dtype=np.complex128))
+        nseg = int(sf.shape[0])
+        cap = 3 * self.n_node + 18 * nseg   # 3x3 diagonal blocks plus two off-diagonal blocks per segment
+        ptr = np.zeros(self.n_node + 1, dtype=np.int32)
+        col = np.zeros(cap, dtype=np.int32)
+        yre = np.zeros(cap)
+        yim = np.zeros(cap)
+        nnz = c_int32()
+        L.call("pf_dist_ybus_from_segments", int(n_bus), nseg, _hptr(sf), _hptr(st), _hptr(z), cap, _hptr(ptr),
+               _hptr(col), _hptr(yre), _hptr(yim), byref(nnz))
+        sl = np.ascontiguousarray(slack_nodes, dtype=np.int32)
+        vs = np.ascontiguousarray(np.asarray(v_slack, dtype=np.complex128))
+        wy = np.ascontiguousarray(wye_nodes, dtype=np.int32)
+        de = np.ascontiguousarray(delta_nodes, dtype=np.int32).reshape(-1, 3)
+        so = _setup_opts(setup)
+        h = c_void_p()
+        L.call("pf_dist_network_create", ctx.h, self.n_node, nnz.value, _hptr(ptr), _hptr(col), _hptr(yre),
+               _hptr(yim), _hptr(sl), _hptr(vs), int(wy.shape[0]), _hptr(wy), int(de.shape[0]), _hptr(de),
+               byref(so), byref(h))
+        self.h = h
+        vals = [c_int32() for _ in range(4)]
+        L.call("pf_dist_network_info", self.h, *[byref(v) for v in vals])
+        self.info = dict(zip(["n_node", "n_free", "n_wye", "n_delta"], [v.value for v in vals]))
+
+    @classmethod
+    def from_feeder(cls, ctx: Context, fd, **setup) -> "DistNetwork":
+        """From a ``workloads.feeder.Feeder`` (substation phases 0, 1, 2 are the slack)."""
+        return cls(ctx, fd.n_bus, fd.seg_from, fd.seg_to, fd.z_seg, [0, 1, 2], fd.v_slack, fd.wye_nodes,
+                   fd.delta_nodes, **setup)
+
+    def close(self) -> None:
+        if self.h:
+            L.lib().pf_dist_network_destroy(self.h)
+            self.h = c_void_p()
+
+    def solve(self, s_wye: torch.Tensor, s_delta: torch.Tensor, *, stream=None, **opts) -> DistResult:
+        """Batched Z-bus fixed point from v0; see pf_dist_solve."""
+        n = self.n_node
+        ld = _ld((s_wye, n, torch.complex128, "s_wye"), (s_delta, n, torch.complex128, "s_delta"))
+        B = int(s_wye.shape[0])
+        dev = s_wye.device
+        v = torch.empty_strided((B, n), (ld, 1), dtype=torch.complex128, device=dev)
+        res = DistResult(v=v, iters=torch.empty(B, dtype=torch.int32, device=dev),
+                         converged=torch.empty(B, dtype=torch.uint8, device=dev),
+                         mismatch=torch.empty(B, dtype=torch.float64, device=dev),
+                         sum_abs_change=torch.empty(B, dtype=torch.float64, device=dev))
+        o = L.opts(**opts)
+        L.call("pf_dist_solve", self.h, byref(o), B, ld, _dptr(s_wye), _dptr(s_delta), _dptr(res.v),
+               _dptr(res.iters), _dptr(res.converged), _dptr(res.mismatch), _dptr(res.sum_abs_change),
+               _stream(stream))
+        return res
+
+
+def precision(name: str) -> int:
+    return {"fp64": L.PF_FP64, "mixed": L.PF_MIXED}[name]

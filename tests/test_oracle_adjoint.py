@@ -24,7 +24,7 @@ def test_dense_adjoint_matches_central_differences():
     batch = tx.make_batch(grid, tx.TX30)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
     col = 3
-    p0, q0, vs = batch.p_inj[:, col], batch.q_inj[:, col], batch.vm_set[:, col]
+    p0, q0, vs = batch.p_inj[col], batch.q_inj[col], batch.vm_set[col]
     res = nr.nr_solve(Y, grid.bus_type, p0, q0, vs, tol=1e-13)
     gp, gq = adjoint.dense_adjoint(grid, res.V)
     h = 1e-6
@@ -54,7 +54,7 @@ def test_two_bus_adjoint_matches_closed_form():
     r, x, P, Q = 0.03, 0.12, 0.8, 0.25
     grid, batch = tx.two_bus(r, x, P, Q)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
-    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[:, 0], batch.q_inj[:, 0], batch.vm_set[:, 0],
+    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[0], batch.q_inj[0], batch.vm_set[0],
                       tol=1e-14)
     gp, gq = adjoint.dense_adjoint(grid, res.V)
 

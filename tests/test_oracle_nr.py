@@ -32,7 +32,7 @@ def two_bus_closed_form(r, x, p, q, v1=1.0):
 def test_two_bus_closed_form(r, x, p, q):
     grid, batch = tx.two_bus(r, x, p, q)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
-    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[:, 0], batch.q_inj[:, 0], batch.vm_set[:, 0],
+    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[0], batch.q_inj[0], batch.vm_set[0],
                       tol=1e-13)
     vm, th = two_bus_closed_form(r, x, p, q)
     assert res.converged
@@ -46,7 +46,7 @@ def test_zero_load_flat_start_is_solution():
     grid.b = np.zeros_like(grid.b)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
     batch = tx.zero_load(grid)
-    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[:, 0], batch.q_inj[:, 0], batch.vm_set[:, 0])
+    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[0], batch.q_inj[0], batch.vm_set[0])
     assert res.converged and res.iters == 0
     assert res.mismatch <= 1e-14
     np.testing.assert_array_equal(res.V, np.ones(grid.n_bus))
@@ -70,7 +70,7 @@ def test_jacobian_matches_central_differences(rng):
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
     theta, pq = nr.index_sets(grid.bus_type)
     batch = tx.make_batch(grid, tx.TX30)
-    p, q = batch.p_inj[:, 0], batch.q_inj[:, 0]
+    p, q = batch.p_inj[0], batch.q_inj[0]
     ang = rng.uniform(-0.2, 0.2, grid.n_bus)
     vm = rng.uniform(0.95, 1.05, grid.n_bus)
     x0 = np.concatenate([ang[theta], vm[pq]])
@@ -99,7 +99,7 @@ def test_nr_matches_independent_solver():
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
     theta, pq = nr.index_sets(grid.bus_type)
     for col in (0, 17, 63):
-        p, q, vs = batch.p_inj[:, col], batch.q_inj[:, col], batch.vm_set[:, col]
+        p, q, vs = batch.p_inj[col], batch.q_inj[col], batch.vm_set[col]
         res = nr.nr_solve(Y, grid.bus_type, p, q, vs, tol=1e-12)
         base_vm = np.where(grid.bus_type == tx.PQ, 1.0, vs)
 
@@ -123,7 +123,7 @@ def test_quadratic_convergence():
     grid = tx.make_grid(tx.TX30)
     batch = tx.make_batch(grid, tx.TX30)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
-    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[:, 5], batch.q_inj[:, 5], batch.vm_set[:, 5],
+    res = nr.nr_solve(Y, grid.bus_type, batch.p_inj[5], batch.q_inj[5], batch.vm_set[5],
                       tol=1e-14)
     h = np.asarray(res.history)
     h = h[h > 1e-13]
@@ -147,9 +147,9 @@ def test_nonconvergence_is_reported():
     grid = tx.make_grid(tx.TX30)
     batch = tx.make_batch(grid, tx.TX30)
     Y = nr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
-    res = nr.nr_solve(Y, grid.bus_type, 50 * batch.p_inj[:, 0], 50 * batch.q_inj[:, 0],
-                      batch.vm_set[:, 0])
+    res = nr.nr_solve(Y, grid.bus_type, 50 * batch.p_inj[0], 50 * batch.q_inj[0],
+                      batch.vm_set[0])
     assert not res.converged
-    res1 = nr.nr_solve(Y, grid.bus_type, batch.p_inj[:, 0], batch.q_inj[:, 0], batch.vm_set[:, 0],
+    res1 = nr.nr_solve(Y, grid.bus_type, batch.p_inj[0], batch.q_inj[0], batch.vm_set[0],
                        max_iter=1)
     assert not res1.converged and res1.iters == 1

@@ -43,7 +43,7 @@ def test_zero_load_gives_no_load_voltage(small_feeder):
     res = zbus.zbus_solve(fd, fdm.zero_load(fd, 2))
     assert res.converged.all() and np.all(res.iters == 1)
     v_rep = np.tile(fd.v_slack, fd.n_bus)
-    assert np.max(np.abs(res.v - v_rep[:, None])) <= 1e-13
+    assert np.max(np.abs(res.v - v_rep[None, :])) <= 1e-13
     # Y v cancels entries of size max|Y| ~ 1e3 pu: rounding leaves ~1e-12
     assert res.mismatch.max() <= 1e-11
 
@@ -54,7 +54,7 @@ def test_power_balance_from_segment_data(small_feeder):
     res = zbus.zbus_solve(fd, batch)
     assert res.converged.all()
     for b in range(batch.batch):
-        v = res.v[:, b].reshape(fd.n_bus, 3)
+        v = res.v[b].reshape(fd.n_bus, 3)
         s_slack = 0.0
         losses = 0.0
         for s in range(fd.n_seg):
@@ -63,7 +63,7 @@ def test_power_balance_from_segment_data(small_feeder):
             losses += np.sum(np.conj(i_seg) * (fd.z_seg[s] @ i_seg))
             if p == 0:
                 s_slack += np.sum(v[0] * np.conj(i_seg))
-        loads = batch.s_wye[:, b].sum() + batch.s_delta[:, b].sum()
+        loads = batch.s_wye[b].sum() + batch.s_delta[b].sum()
         assert abs(s_slack - (loads + losses)) <= 1e-9 * abs(s_slack)
 
 
@@ -89,7 +89,7 @@ def test_balanced_segment_reduces_to_two_bus(kind):
     va = _closed_form_phase_a(z_self * (1 - kappa), s)
     a = np.exp(-2j * np.pi / 3)
     expect = np.array([va, va * a, va * a * a])
-    assert np.max(np.abs(res.v[3:6, 0] - expect)) <= 1e-12
+    assert np.max(np.abs(res.v[0, 3:6] - expect)) <= 1e-12
 
 
 def test_delta_and_wye_injection_conserve_power(rng):

@@ -51,8 +51,8 @@ def test_batches_are_deterministic():
     _same(tx.make_batch(g, tx.TX30), tx.make_batch(g, tx.TX30))
     b = tx.make_batch(g, tx.TX30)
     pq = g.bus_type == tx.PQ
-    ratio = b.p_inj[pq] / (-g.p_load[pq][:, None])
-    np.testing.assert_allclose(ratio, ratio[0:1].repeat(ratio.shape[0], 0))   # one factor per scenario
+    ratio = b.p_inj[:, pq] / (-g.p_load[pq][None, :])
+    np.testing.assert_allclose(ratio, ratio[:, 0:1].repeat(ratio.shape[1], 1))   # one factor per scenario
 
 
 def test_tx30_all_scenarios_converge_in_oracle():

@@ -15,7 +15,7 @@ Per-unit system: line-to-line base 4.16 kV, three-phase base 1 MVA; per-phase
 quantities use the line-to-neutral voltage base and one third of the power
 base, so the impedance base is 4.16^2 / 1 = 17.3056 ohm.
 
-Load arrays are ``[n_node, batch]`` complex, scenario index contiguous, in the
+Load arrays are ``[batch, n_node]`` complex (one row per scenario), in the
 consumption convention.  ``s_wye[node]`` is the wye load on that phase node.
 For a delta bus with nodes (a, b, c), ``s_delta[a]``, ``s_delta[b]`` and
 ``s_delta[c]`` hold the loads of the ab, bc and ca branches.
@@ -67,13 +67,13 @@ class Feeder:
 
 @dataclass
 class FeederBatch:
-    s_wye: np.ndarray         # complex128 [n_node, B]
-    s_delta: np.ndarray       # complex128 [n_node, B]
+    s_wye: np.ndarray         # complex128 [B, n_node]
+    s_delta: np.ndarray       # complex128 [B, n_node]
     meta: dict = field(default_factory=dict)
 
     @property
     def batch(self) -> int:
-        return int(self.s_wye.shape[1])
+        return int(self.s_wye.shape[0])
 
 
 @dataclass(frozen=True)
@@ -147,9 +147,9 @@ def make_batch(feeder: Feeder, cfg: FeederConfig, batch: int | None = None,
     """Independent U(1 - spread, 1 + spread) multiplier per load phase and scenario."""
     B = cfg.batch if batch is None else int(batch)
     rng = np.random.default_rng(cfg.seed + 1 if seed is None else seed)
-    mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (feeder.n_node, B))
-    s_wye = feeder.s_base_wye[:, None] * mult
-    s_delta = feeder.s_base_delta[:, None] * mult
+    mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (B, feeder.n_node))
+    s_wye = feeder.s_base_wye[None, :] * mult
+    s_delta = feeder.s_base_delta[None, :] * mult
     return FeederBatch(s_wye=np.ascontiguousarray(s_wye), s_delta=np.ascontiguousarray(s_delta),
                        meta={"config": cfg.name, "batch": B})
 
@@ -173,11 +173,11 @@ def single_segment(z_self: complex, kappa: float, kind: int, s_phase: complex,
                 s_base_wye=s if kind == 1 else np.zeros(6, dtype=np.complex128),
                 s_base_delta=s if kind == 2 else np.zeros(6, dtype=np.complex128),
                 v_slack=np.array([1.0, a, a * a]), name="single_segment")
-    sw = np.repeat(fd.s_base_wye[:, None], batch, axis=1)
-    sd = np.repeat(fd.s_base_delta[:, None], batch, axis=1)
+    sw = np.repeat(fd.s_base_wye[None, :], batch, axis=0)
+    sd = np.repeat(fd.s_base_delta[None, :], batch, axis=0)
     return fd, FeederBatch(s_wye=sw, s_delta=sd)
 
 
 def zero_load(feeder: Feeder, batch: int = 1) -> FeederBatch:
-    z = np.zeros((feeder.n_node, batch), dtype=np.complex128)
+    z = np.zeros((batch, feeder.n_node), dtype=np.complex128)
     return FeederBatch(s_wye=z.copy(), s_delta=z.copy())

@@ -10,8 +10,9 @@ buses plus extra lines), pi-model lines, PQ loads with a fixed power factor and
 PV generators with voltage set-points.  Scenario batches perturb the loads (and PV dispatch) per scenario,
 as the paper's case studies do with random load multipliers (Sec. III).
 
-Array layout: every per-bus, per-scenario quantity is ``[n_bus, batch]`` with the
-scenario index contiguous, which is the layout the device library consumes.
+Array layout: every per-scenario, per-bus quantity is ``[batch, n_bus]``
+(scenario-major, one contiguous row per scenario), the layout the device
+library consumes.
 Injections follow the generator convention (generation minus load).
 """
 from __future__ import annotations
@@ -57,16 +58,16 @@ class TxGrid:
 
 @dataclass
 class TxBatch:
-    """A batch of scenarios on one grid, scenario index contiguous."""
+    """A batch of scenarios on one grid, one row per scenario."""
 
-    p_inj: np.ndarray         # float64 [n, B]: scheduled active injection
-    q_inj: np.ndarray         # float64 [n, B]: scheduled reactive injection
-    vm_set: np.ndarray        # float64 [n, B]: |V| set-points (PV, slack); 1.0 elsewhere
+    p_inj: np.ndarray         # float64 [B, n]: scheduled active injection
+    q_inj: np.ndarray         # float64 [B, n]: scheduled reactive injection
+    vm_set: np.ndarray        # float64 [B, n]: |V| set-points (PV, slack); 1.0 elsewhere
     meta: dict = field(default_factory=dict)
 
     @property
     def batch(self) -> int:
-        return int(self.p_inj.shape[1])
+        return int(self.p_inj.shape[0])
 
 
 @dataclass(frozen=True)
@@ -224,16 +225,16 @@ def make_batch(grid: TxGrid, cfg: TxConfig, batch: int | None = None, seed: int 
     n = grid.n_bus
     if cfg.perturbation == "lognormal":
         fac = np.exp(rng.normal(0.0, cfg.sigma, B))
-        load_mult = np.broadcast_to(fac[None, :], (n, B))
-        gen_mult = np.ones((n, B))
+        load_mult = np.broadcast_to(fac[:, None], (B, n))
+        gen_mult = np.ones((B, n))
     elif cfg.perturbation == "uniform":
-        load_mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (n, B))
-        gen_mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (n, B))
+        load_mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (B, n))
+        gen_mult = rng.uniform(1.0 - cfg.spread, 1.0 + cfg.spread, (B, n))
     else:
         raise ValueError(cfg.perturbation)
-    p = grid.p_gen[:, None] * gen_mult - grid.p_load[:, None] * load_mult
-    q = -grid.q_load[:, None] * load_mult
-    vm = np.broadcast_to(grid.vm_set[:, None], (n, B))
+    p = grid.p_gen[None, :] * gen_mult - grid.p_load[None, :] * load_mult
+    q = -grid.q_load[None, :] * load_mult
+    vm = np.broadcast_to(grid.vm_set[None, :], (B, n))
     return TxBatch(p_inj=np.ascontiguousarray(p), q_inj=np.ascontiguousarray(q),
                    vm_set=np.ascontiguousarray(vm), meta={"config": cfg.name, "batch": B})
 
@@ -245,15 +246,15 @@ def two_bus(r: float, x: float, p_load: float, q_load: float, batch: int = 1) ->
                   r=np.array([r]), x=np.array([x]), b=np.array([0.0]),
                   vm_set=np.ones(2), p_load=np.array([0.0, p_load]),
                   q_load=np.array([0.0, q_load]), p_gen=np.zeros(2), slack=0, name="two_bus")
-    p = np.zeros((2, batch))
-    q = np.zeros((2, batch))
-    p[1] = -p_load
-    q[1] = -q_load
-    return grid, TxBatch(p_inj=p, q_inj=q, vm_set=np.ones((2, batch)))
+    p = np.zeros((batch, 2))
+    q = np.zeros((batch, 2))
+    p[:, 1] = -p_load
+    q[:, 1] = -q_load
+    return grid, TxBatch(p_inj=p, q_inj=q, vm_set=np.ones((batch, 2)))
 
 
 def zero_load(grid: TxGrid, batch: int = 1) -> TxBatch:
     """No load and no dispatch anywhere, all set-points 1.0."""
     n = grid.n_bus
-    return TxBatch(p_inj=np.zeros((n, batch)), q_inj=np.zeros((n, batch)),
-                   vm_set=np.ones((n, batch)))
+    return TxBatch(p_inj=np.zeros((batch, n)), q_inj=np.zeros((batch, n)),
+                   vm_set=np.ones((batch, n)))
