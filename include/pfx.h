@@ -137,14 +137,20 @@ pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* 
  * read only there).  Device outputs: v_out complex [batch][ld] (all buses),
  * newton_iters[batch] (updates taken), gmres_iters[batch] (Arnoldi steps over
  * all Newton steps), converged[batch] (1 when max |F| <= tol),
- * final_mismatch[batch] (max |F| at v_out).  Optional outputs may be null:
- * gmres_iters, final_mismatch.  batch may be 0 (no work).
+ * final_mismatch[batch] (max |F| at v_out), work_bytes[batch] (algorithmic
+ * HBM bytes of the scenario's solve under the byte model: per Jacobian-vector
+ * product 2wm + 32n, per preconditioner application 2wm + 8n, per Arnoldi
+ * step j (4j + 6)wm, per GMRES cycle start 8m + wm and end (k + 2)wm for k
+ * steps, per mismatch evaluation 32n + 16m, per Newton update 16m, with
+ * w = 8 (PF_FP64) or 4 (PF_MIXED) and m = |Theta| + |Q|).  Optional outputs
+ * may be null: gmres_iters, final_mismatch, work_bytes.  batch may be 0.
  * Errors: PF_INVALID_ARG (ld < n_bus, batch < 0, bad options),
  * PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_tx_solve(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
                       const double* p_inj, const double* q_inj, const double* vm_set,
                       double* v_out, int32_t* newton_iters, int32_t* gmres_iters,
-                      uint8_t* converged, double* final_mismatch, pf_stream stream);
+                      uint8_t* converged, double* final_mismatch, double* work_bytes,
+                      pf_stream stream);
 
 /* Branch loss L_b = sum over branches of |I_f|^2 with the from-end current
  * I_f = (y_s + j b/2) V_f - y_s V_t, for voltages v (device complex

@@ -110,9 +110,11 @@ def residual(feeder, v_all, s_wye, s_delta):
     return r, vN * np.conj(r)
 
 
-def zbus_solve(feeder, batch, tol_v=1e-13, max_iter=200):
-    """Run v <- Z i(v) + v0 from v0 for every scenario of the batch (eq. (10))."""
-    Z, v0, N = zbus(feeder)
+def zbus_solve(feeder, batch, tol_v=1e-13, max_iter=200, setup=None):
+    """Run v <- Z i(v) + v0 from v0 for every scenario of the batch (eq. (10)).
+
+    ``setup`` may pass a precomputed ``zbus(feeder)`` result."""
+    Z, v0, N = zbus(feeder) if setup is None else setup
     dN = _nonslack_delta(feeder, N)
     sw = batch.s_wye.T[N]
     sd = batch.s_delta.T[N]

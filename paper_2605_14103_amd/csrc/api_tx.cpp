@@ -103,7 +103,7 @@ pf_status pf_tx_network_info(const pf_tx_network* h, int32_t* n_bus, int32_t* n_
 pf_status pf_tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld,
                       const double* p_inj, const double* q_inj, const double* vm_set, double* v_out,
                       int32_t* newton_iters, int32_t* gmres_iters, uint8_t* converged,
-                      double* final_mismatch, pf_stream stream) {
+                      double* final_mismatch, double* work_bytes, pf_stream stream) {
   return guarded([&] {
     TxNetwork* net = tx_of(h);
     const pf_opts o = resolve_opts(opts);
@@ -127,6 +127,7 @@ pf_status pf_tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int6
     a.gmres_iters = gmres_iters;
     a.converged = converged;
     a.final_mismatch = final_mismatch;
+    a.work_bytes = work_bytes;
     a.tol = o.tol;
     a.diverge = o.diverge;
     a.rtol = o.gmres_rtol;

@@ -381,9 +381,25 @@ __device__ Smem<T> carve(unsigned char* smem, const NrLayout& L) {
 // inside a cycle), after max_restarts cycles, or at a breakdown.  Returns the
 // number of Arnoldi steps; *converged tells whether the tolerance was met.
 // Orthogonalisation: classical Gram-Schmidt with one re-orthogonalisation.
+// Algorithmic HBM bytes of one scenario (the byte model reported with the
+// solve): with w = sizeof(T), per Jacobian-vector product 2 w m + 32 n, per
+// preconditioner application 2 w m + 8 n, per Arnoldi step j (orthogonalising
+// against j + 1 vectors by CGS2) (4 j + 6) w m, per cycle end (k + 2) w m, per
+// cycle start 8 m + w m, per mismatch evaluation 32 n + 16 m and per Newton
+// update 16 m.
+struct ByteModel {
+  double wm, m8, n8;
+  __device__ double jvp() const { return 2 * wm + 4 * n8; }
+  __device__ double pre() const { return 2 * wm + n8; }
+  __device__ double orth(int j) const { return (4.0 * j + 6.0) * wm; }
+  __device__ double mismatch() const { return 4 * n8 + 2 * m8; }
+  __device__ double update() const { return 2 * m8; }
+};
+
 template <typename T, int BLOCK, int K, typename ApplyA, typename ApplyM>
 __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs, T* basis, int m, int R,
-                           int max_restarts, T rtol, double (&x)[K], const Smem<T>& s, bool* converged) {
+                           int max_restarts, T rtol, double (&x)[K], const Smem<T>& s, bool* converged,
+                           const ByteModel& bm, double* work) {
   T w[K];
   T beta0 = 0;
   int total = 0;
@@ -391,6 +407,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll
   for (int k = 0; k < K; ++k) x[k] = 0.0;
   for (int cycle = 0; cycle < max_restarts && !done; ++cycle) {
+    *work += (cycle > 0 ? bm.jvp() : 0.0) + bm.pre() + bm.m8 + bm.wm;
     if (cycle == 0) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
@@ -430,6 +447,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
     for (int j = 0; j < R; ++j) {
       apply_a(w);
       apply_m(w);
+      *work += bm.jvp() + bm.pre() + bm.orth(j);
       multi_dot<T, BLOCK, K>(basis, m, j + 1, m, w, s.red, s.h1);
       subtract_proj<T, BLOCK, K>(basis, m, j + 1, m, w, s.h1);
       multi_dot<T, BLOCK, K>(basis, m, j + 1, m, w, s.red, s.h2);
@@ -472,6 +490,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
       }
     }
     total += steps;
+    *work += (steps + 2) * bm.wm;
     // y = H^-1 g (upper triangular after the rotations)
     if (threadIdx.x == 0) {
       for (int i = steps - 1; i >= 0; --i) {
@@ -530,7 +549,10 @@ __global__ __launch_bounds__(BLOCK) void nr_kernel(TxDev<double> ynet, TxDev<T> 
   int newton = 0, gtotal = 0;
   bool conv = false;
   double fnorm = 0.0;
+  const ByteModel bm{(double)sizeof(T) * m, 8.0 * m, 8.0 * n};
+  double work = 0.0;
   for (;;) {
+    work += bm.mismatch();
     fnorm = mismatch<BLOCK, K>(ynet, n, nth, npq, m, sc, P, Q, int2ext, s.vs, s.redd);
     if (!(fnorm <= a.diverge)) break;
     if (fnorm <= a.tol) {
@@ -547,7 +569,8 @@ __global__ __launch_bounds__(BLOCK) void nr_kernel(TxDev<double> ynet, TxDev<T> 
     double dx[K];
     bool lin_ok;
     gtotal += gmres_solve<T, BLOCK, K>(apply_j, apply_m, sc.F, basis, m, R, a.max_restarts, (T)a.rtol,
-                                       dx, s, &lin_ok);
+                                       dx, s, &lin_ok, bm, &work);
+    work += bm.update();
     // Newton update (eq. (3)), FP64
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -570,6 +593,7 @@ __global__ __launch_bounds__(BLOCK) void nr_kernel(TxDev<double> ynet, TxDev<T> 
     if (a.gmres_iters) a.gmres_iters[b] = gtotal;
     a.converged[b] = conv ? 1 : 0;
     if (a.final_mismatch) a.final_mismatch[b] = fnorm;
+    if (a.work_bytes) a.work_bytes[b] = work;
   }
 }
 
@@ -718,8 +742,10 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(TxDev<double> net, const
   auto apply_mt = [&](double (&w)[K]) { precond_t<BLOCK, K>(net, sc.vm, w, s.xs, s.tmp); };
   double lam[K];
   bool ok;
+  const ByteModel bm{8.0 * m, 8.0 * m, 8.0 * n};
+  double work = 0.0;
   const int its = gmres_solve<double, BLOCK, K>(apply_jt, apply_mt, sc.F, basis, m, R, a.max_restarts, a.rtol,
-                                                lam, s, &ok);
+                                                lam, s, &ok, bm, &work);
   double* gp = a.grad_p + (int64_t)b * a.ld;
   double* gq = a.grad_q + (int64_t)b * a.ld;
   // zero the rows that carry no state (the slack's P, the Q of PV buses and the slack)

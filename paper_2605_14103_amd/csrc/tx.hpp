@@ -99,6 +99,7 @@ struct NRLaunch {
   int32_t* gmres_iters;
   uint8_t* converged;
   double* final_mismatch;
+  double* work_bytes;
   double tol, diverge, rtol;
   int max_newton, restart, max_restarts;
   double* ws_d;

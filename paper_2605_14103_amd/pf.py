@@ -90,6 +90,7 @@ class TxResult:
     gmres_iters: torch.Tensor    # int32 (batch,)
     converged: torch.Tensor      # uint8 (batch,)
     mismatch: torch.Tensor       # float64 (batch,)
+    work_bytes: torch.Tensor | None = None   # float64 (batch,): algorithmic HBM bytes per solve
 
 
 class TxNetwork:
@@ -149,13 +150,14 @@ class TxNetwork:
                            newton_iters=torch.empty(B, dtype=torch.int32, device=dev),
                            gmres_iters=torch.empty(B, dtype=torch.int32, device=dev),
                            converged=torch.empty(B, dtype=torch.uint8, device=dev),
-                           mismatch=torch.empty(B, dtype=torch.float64, device=dev))
+                           mismatch=torch.empty(B, dtype=torch.float64, device=dev),
+                           work_bytes=torch.empty(B, dtype=torch.float64, device=dev))
         if B > 1 and out.v.stride(0) != ld:
             raise ValueError("output rows must use the input row stride")
         o = L.opts(**opts)
         L.call("pf_tx_solve", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
                _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters), _dptr(out.converged),
-               _dptr(out.mismatch), _stream(stream))
+               _dptr(out.mismatch), _dptr(out.work_bytes), _stream(stream))
         return out
 
     def branch_loss(self, v: torch.Tensor, *, grad: bool = True, stream=None):
