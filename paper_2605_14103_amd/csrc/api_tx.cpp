@@ -113,7 +113,7 @@ pf_status pf_tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int6
     activate(net->ctx);
     const bool mixed = o.precision == PF_MIXED;
     const int64_t dstride = nr_ws_doubles(*net);
-    const int64_t bstride = (int64_t)(o.gmres_restart + 1) * net->m;
+    const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
     net->ws_d.ensure(net->ctx, (size_t)batch * dstride * sizeof(double));
     net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
     NRLaunch a{};
@@ -168,7 +168,7 @@ pf_status pf_tx_adjoint(pf_tx_network* h, const pf_opts* opts, int32_t batch, in
     activate(net->ctx);
     const double rtol = (opts && opts->gmres_rtol > 0) ? opts->gmres_rtol : 1e-10;
     const int64_t dstride = adj_ws_doubles(*net);
-    const int64_t bstride = (int64_t)(o.gmres_restart + 1) * net->m;
+    const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
     net->ws_adj.ensure(net->ctx, (size_t)batch * (dstride + bstride) * sizeof(double));
     AdjLaunch a{};
     a.batch = batch;

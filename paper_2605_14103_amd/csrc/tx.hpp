@@ -51,6 +51,10 @@ struct TxDev {
   const int* gt_ptr;     // G^T; rows Theta, columns as factor positions of bpp
   const int* gt_col;
   const T* gt_val;
+  const int* yt_ptr;     // Ybus^T CSR (internal order), for the adjoint
+  const int* yt_col;
+  const double* yt_re;
+  const double* yt_im;
   // branch list (internal bus numbers) for the branch-current loss
   int n_branch;
   const int* br_f;
@@ -83,8 +87,14 @@ struct TxNetwork {
   DeviceBuffer inc_ptr, inc_br;   // branches incident to each internal bus
   // solve workspaces (grow-only); calls on one network must not overlap
   DeviceBuffer ws_d, ws_basis, ws_adj;
+  // the device views themselves, resident in device memory so kernels take one pointer
+  DeviceBuffer desc64, desc32;
   template <typename T>
   TxDev<T> view() const;
+  template <typename T>
+  const TxDev<T>* desc() const {
+    return sizeof(T) == 8 ? desc64.as<const TxDev<T>>() : desc32.as<const TxDev<T>>();
+  }
 };
 
 // Launchers (nr_kernels.hip).
@@ -108,8 +118,10 @@ struct NRLaunch {
   int64_t ws_b_stride;
 };
 
-// Doubles of per-scenario FP64 workspace the NR kernel needs.
+// Doubles of per-scenario FP64 workspace the NR kernel needs, and the padded
+// state length (rows per thread times threads) of its vectors.
 int64_t nr_ws_doubles(const TxNetwork& net);
+int64_t nr_padded_rows(const TxNetwork& net);
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s);
 
 struct LossLaunch {

@@ -142,6 +142,10 @@ TxDev<T> TxNetwork::view() const {
   d.br_ys_re = br_ys_re.as<double>();
   d.br_ys_im = br_ys_im.as<double>();
   d.br_b = br_b.as<double>();
+  d.yt_ptr = yt_ptr.as<int>();
+  d.yt_col = yt_col.as<int>();
+  d.yt_re = yt_re.as<double>();
+  d.yt_im = yt_im.as<double>();
   return d;
 }
 
@@ -320,6 +324,8 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
   }
   net->inc_ptr = upload(ctx, iptr);
   net->inc_br = upload(ctx, ibr);
+  net->desc64 = upload(ctx, std::vector<TxDev<double>>{net->view<double>()});
+  net->desc32 = upload(ctx, std::vector<TxDev<float>>{net->view<float>()});
   return net.release();
 }
 
