@@ -114,6 +114,24 @@ __device__ __forceinline__ unsigned row(int k) {
   return threadIdx.x + (unsigned)k * BLOCK;
 }
 
+// Global-memory element access by a 32-bit index from a base pointer that is
+// uniform across the workgroup: the byte offset stays 32-bit and the pointer
+// is tagged global, so the scalar-base plus vector-offset form is used instead
+// of a 64-bit address per element.
+template <typename T>
+__device__ __forceinline__ T gld(const T* base, unsigned i) {
+  typedef __attribute__((address_space(1))) const char GC;
+  typedef __attribute__((address_space(1))) const T GT;
+  return *(GT*)((GC*)base + i * (unsigned)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(T* base, unsigned i, T v) {
+  typedef __attribute__((address_space(1))) char GC;
+  typedef __attribute__((address_space(1))) T GT;
+  *(GT*)((GC*)base + i * (unsigned)sizeof(T)) = v;
+}
+
 struct NrLayout {
   int xs, tmp, red, h1, h2, H, cs, sn, g, y, misc, total;
 };
@@ -190,11 +208,12 @@ __device__ Smem<T> carve(unsigned char* smem, const NrLayout& L) {
 template <typename T, int BLOCK>
 __device__ void spd_apply(const SpdDev<T>& f, T* xs, T* tmp) {
   for (int l = 0; l < f.nfl; ++l) {
-    const int s = f.f_lev[l], e = f.f_lev[l + 1];
+    const int s = gld(f.f_lev, l), e = gld(f.f_lev, l + 1);
     for (int q = s + (int)threadIdx.x; q < e; q += BLOCK) {
-      const int i = f.f_rows[q];
+      const int i = gld(f.f_rows, q);
       T a = xs[i];
-      for (int p = f.L_ptr[i]; p < f.L_ptr[i + 1]; ++p) a -= f.L_val[p] * xs[f.L_col[p]];
+      const int pe = gld(f.L_ptr, i + 1);
+      for (int p = gld(f.L_ptr, i); p < pe; ++p) a -= gld(f.L_val, p) * xs[gld(f.L_col, p)];
       xs[i] = a;
     }
     __syncthreads();
@@ -202,30 +221,32 @@ __device__ void spd_apply(const SpdDev<T>& f, T* xs, T* tmp) {
   if (f.k > 0) {
     for (int i = f.c + (int)threadIdx.x; i < f.N; i += BLOCK) {
       T a = xs[i];
-      for (int p = f.L_ptr[i]; p < f.L_ptr[i + 1]; ++p) a -= f.L_val[p] * xs[f.L_col[p]];
+      const int pe = gld(f.L_ptr, i + 1);
+      for (int p = gld(f.L_ptr, i); p < pe; ++p) a -= gld(f.L_val, p) * xs[gld(f.L_col, p)];
       tmp[i - f.c] = a;
     }
     __syncthreads();
     for (int i = (int)threadIdx.x; i < f.k; i += BLOCK) {
       T a0 = 0, a1 = 0;
-      const T* col = f.Sinv + i;
+      unsigned o = i;
       int l = 0;
-      for (; l + 1 < f.k; l += 2) {
-        a0 += col[(size_t)l * f.k] * tmp[l];
-        a1 += col[(size_t)(l + 1) * f.k] * tmp[l + 1];
+      for (; l + 1 < f.k; l += 2, o += 2 * f.k) {
+        a0 += gld(f.Sinv, o) * tmp[l];
+        a1 += gld(f.Sinv, o + f.k) * tmp[l + 1];
       }
-      if (l < f.k) a0 += col[(size_t)l * f.k] * tmp[l];
+      if (l < f.k) a0 += gld(f.Sinv, o) * tmp[l];
       xs[f.c + i] = a0 + a1;
     }
   }
-  for (int j = (int)threadIdx.x; j < f.c; j += BLOCK) xs[j] *= f.dinv[j];
+  for (int j = (int)threadIdx.x; j < f.c; j += BLOCK) xs[j] *= gld(f.dinv, j);
   __syncthreads();
   for (int l = 0; l < f.nbl; ++l) {
-    const int s = f.b_lev[l], e = f.b_lev[l + 1];
+    const int s = gld(f.b_lev, l), e = gld(f.b_lev, l + 1);
     for (int q = s + (int)threadIdx.x; q < e; q += BLOCK) {
-      const int j = f.b_rows[q];
+      const int j = gld(f.b_rows, q);
       T a = xs[j];
-      for (int p = f.T_ptr[j]; p < f.T_ptr[j + 1]; ++p) a -= f.T_val[p] * xs[f.T_col[p]];
+      const int pe = gld(f.T_ptr, j + 1);
+      for (int p = gld(f.T_ptr, j); p < pe; ++p) a -= gld(f.T_val, p) * xs[gld(f.T_col, p)];
       xs[j] = a;
     }
     __syncthreads();
@@ -263,7 +284,7 @@ __device__ void precond(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], 
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const unsigned r = row<BLOCK>(k);
-    if (k < kd && r < nth) x1[net.bp.pinv[r]] = w[k] * (T)sc.ivm[r];
+    if (k < kd && r < nth) x1[gld(net.bp.pinv, r)] = w[k] * (T)gld(sc.ivm, r);
   }
   __syncthreads();
   spd_apply<T, BLOCK>(net.bp, x1, tmp);
@@ -274,8 +295,9 @@ __device__ void precond(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], 
       if (r >= nth && r < m) {
         const unsigned q = r - nth;
         T t = rget(w, k);
-        for (int p = net.g_ptr[q]; p < net.g_ptr[q + 1]; ++p) t -= net.g_val[p] * x1[net.g_col[p]];
-        x2[net.bpp.pinv[q]] = t * (T)sc.ivm[q];
+        const int pe = gld(net.g_ptr, q + 1);
+        for (int p = gld(net.g_ptr, q); p < pe; ++p) t -= gld(net.g_val, p) * x1[gld(net.g_col, p)];
+        x2[gld(net.bpp.pinv, q)] = t * (T)gld(sc.ivm, q);
       }
     }
     __syncthreads();
@@ -285,8 +307,8 @@ __device__ void precond(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], 
   for (int k = 0; k < K; ++k) {
     const unsigned r = row<BLOCK>(k);
     if (k < kd) {
-      if (r < nth) w[k] = x1[net.bp.pinv[r]];
-      else if (r < m) w[k] = x2[net.bpp.pinv[r - nth]];
+      if (r < nth) w[k] = x1[gld(net.bp.pinv, r)];
+      else if (r < m) w[k] = x2[gld(net.bpp.pinv, r - nth)];
     }
   }
   __syncthreads();
@@ -306,8 +328,8 @@ __device__ void jvp(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], T* x
   // dV_b = V_b (j p_theta + p_|V| / |V|)
   auto dv = [&](int bus, T& dr, T& di) {
     const T pth = bus < nth ? xs[bus] : (T)0;
-    const T a = bus < npq ? xs[nth + bus] * (T)sc.ivm[bus] : (T)0;
-    const T vr = (T)sc.vre[bus], vi = (T)sc.vim[bus];
+    const T a = bus < npq ? xs[nth + bus] * (T)gld(sc.ivm, bus) : (T)0;
+    const T vr = (T)gld(sc.vre, bus), vi = (T)gld(sc.vim, bus);
     dr = vr * a - vi * pth;
     di = vi * a + vr * pth;
   };
@@ -317,17 +339,18 @@ __device__ void jvp(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], T* x
     if (r < m) {
       const int i = (int)r < nth ? (int)r : (int)r - nth;
       T dIr = 0, dIi = 0;
-      for (int p = net.y_ptr[i]; p < net.y_ptr[i + 1]; ++p) {
+      const int pe = gld(net.y_ptr, i + 1);
+      for (int p = gld(net.y_ptr, i); p < pe; ++p) {
         T dr, di;
-        dv(net.y_col[p], dr, di);
-        const T yr = (T)net.y_re[p], yi = (T)net.y_im[p];
+        dv(gld(net.y_col, p), dr, di);
+        const T yr = (T)gld(net.y_re, p), yi = (T)gld(net.y_im, p);
         dIr += yr * dr - yi * di;
         dIi += yr * di + yi * dr;
       }
       T dVr, dVi;
       dv(i, dVr, dVi);
-      const T Ir = (T)sc.ire[i], Ii = (T)sc.iim[i];
-      const T vr = (T)sc.vre[i], vi = (T)sc.vim[i];
+      const T Ir = (T)gld(sc.ire, i), Ii = (T)gld(sc.iim, i);
+      const T vr = (T)gld(sc.vre, i), vi = (T)gld(sc.vim, i);
       // dS = dV conj(I) + V conj(dI): real part on Theta rows, imaginary on Q rows
       rset(w, k, (int)r < nth ? dVr * Ir + dVi * Ii + vr * dIr + vi * dIi
                               : dVi * Ir - dVr * Ii + vi * dIr - vr * dIi);
@@ -350,9 +373,10 @@ __device__ void multi_dot(const T* basis, unsigned stride, int nv, int kd, const
     T a0 = 0, a1 = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      if (k >= kd) break;
-      a0 += v0[row<BLOCK>(k)] * w[k];
-      a1 += v1[row<BLOCK>(k)] * w[k];
+      if (k < kd) {
+        a0 += gld(v0, row<BLOCK>(k)) * w[k];
+        a1 += gld(v1, row<BLOCK>(k)) * w[k];
+      }
     }
     a0 = wave_sum(a0);
     a1 = wave_sum(a1);
@@ -365,10 +389,8 @@ __device__ void multi_dot(const T* basis, unsigned stride, int nv, int kd, const
     const T* v0 = basis + (unsigned)i * stride;
     T a0 = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k >= kd) break;
-      a0 += v0[row<BLOCK>(k)] * w[k];
-    }
+    for (int k = 0; k < K; ++k)
+      if (k < kd) a0 += gld(v0, row<BLOCK>(k)) * w[k];
     a0 = wave_sum(a0);
     if (lane == 0) red[i * NW + wid] = a0;
   }
@@ -396,19 +418,15 @@ __device__ void subtract_proj(const T* basis, unsigned stride, int nv, int kd, T
     const T* v0 = basis + (unsigned)i * stride;
     const T* v1 = v0 + stride;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k >= kd) break;
-      w[k] -= h0 * v0[row<BLOCK>(k)] + h1 * v1[row<BLOCK>(k)];
-    }
+    for (int k = 0; k < K; ++k)
+      if (k < kd) w[k] -= h0 * gld(v0, row<BLOCK>(k)) + h1 * gld(v1, row<BLOCK>(k));
   }
   if (i < nv) {
     const T h0 = h[i];
     const T* v0 = basis + (unsigned)i * stride;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k >= kd) break;
-      w[k] -= h0 * v0[row<BLOCK>(k)];
-    }
+    for (int k = 0; k < K; ++k)
+      if (k < kd) w[k] -= h0 * gld(v0, row<BLOCK>(k));
   }
 }
 
@@ -421,12 +439,12 @@ __device__ double mismatch(const TxDev<T>& net, const Scen& sc, int kd, const do
   const int* ext = net.int2ext;
   for (int i = threadIdx.x; i < n; i += BLOCK) {
     double s, c;
-    sincos(sc.th[i], &s, &c);
-    const double vm = sc.vm[i];
+    sincos(gld(sc.th, i), &s, &c);
+    const double vm = gld(sc.vm, i);
     const double vr = vm * c, vi = vm * s;
-    sc.vre[i] = vr;
-    sc.vim[i] = vi;
-    sc.ivm[i] = 1.0 / vm;
+    gst(sc.vre, i, vr);
+    gst(sc.vim, i, vi);
+    gst(sc.ivm, i, 1.0 / vm);
     vs[2 * i] = vr;
     vs[2 * i + 1] = vi;
   }
@@ -436,13 +454,14 @@ __device__ double mismatch(const TxDev<T>& net, const Scen& sc, int kd, const do
   for (int k = 0; k < kd; ++k) {
     const int r = (int)row<BLOCK>(k);
     if (r >= m) {
-      sc.F[r] = 0.0;  // padding rows of the right-hand side stay zero
+      gst(sc.F, r, 0.0);  // padding rows of the right-hand side stay zero
     } else {
       const int i = r < nth ? r : r - nth;
       double Ir = 0.0, Ii = 0.0;
-      for (int p = net.y_ptr[i]; p < net.y_ptr[i + 1]; ++p) {
-        const int c = net.y_col[p];
-        const double yr = net.y_re[p], yi = net.y_im[p];
+      const int pe = gld(net.y_ptr, i + 1);
+      for (int p = gld(net.y_ptr, i); p < pe; ++p) {
+        const int c = gld(net.y_col, p);
+        const double yr = gld(net.y_re, p), yi = gld(net.y_im, p);
         const double vr = vs[2 * c], vi = vs[2 * c + 1];
         Ir += yr * vr - yi * vi;
         Ii += yr * vi + yi * vr;
@@ -450,13 +469,13 @@ __device__ double mismatch(const TxDev<T>& net, const Scen& sc, int kd, const do
       const double vr = vs[2 * i], vi = vs[2 * i + 1];
       double f;
       if (r < nth) {
-        sc.ire[i] = Ir;
-        sc.iim[i] = Ii;
-        f = vr * Ir + vi * Ii - P[ext[i]];
+        gst(sc.ire, i, Ir);
+        gst(sc.iim, i, Ii);
+        f = vr * Ir + vi * Ii - gld(P, gld(ext, i));
       } else {
-        f = vi * Ir - vr * Ii - Q[ext[i]];
+        f = vi * Ir - vr * Ii - gld(Q, gld(ext, i));
       }
-      sc.F[r] = f;
+      gst(sc.F, r, f);
       fmax = nanmax(fmax, fabs(f));
     }
   }
@@ -496,22 +515,22 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     w[k] = 0;
-    if (k < kd) x[row<BLOCK>(k)] = 0.0;
+    if (k < kd) gst(x, row<BLOCK>(k), 0.0);
   }
   for (int cycle = 0; cycle < max_restarts && !done; ++cycle) {
     *work += (cycle > 0 ? bm.jvp() : 0.0) + bm.pre() + bm.m8 + bm.wm;
     if (cycle == 0) {
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)rhs[row<BLOCK>(k)];
+        if (k < kd) w[k] = (T)gld(rhs, row<BLOCK>(k));
     } else {
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)x[row<BLOCK>(k)];
+        if (k < kd) w[k] = (T)gld(x, row<BLOCK>(k));
       apply_a(w);
 #pragma unroll
       for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)rhs[row<BLOCK>(k)] - w[k];
+        if (k < kd) w[k] = (T)gld(rhs, row<BLOCK>(k)) - w[k];
     }
     apply_m(w);
     T ss = 0;
@@ -527,7 +546,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       w[k] *= ib;
-      if (k < kd) basis[row<BLOCK>(k)] = w[k];
+      if (k < kd) gst(basis, row<BLOCK>(k), w[k]);
     }
     if (threadIdx.x == 0) s.g[0] = beta;
     int steps = 0;
@@ -585,7 +604,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         w[k] *= ih;
-        if (k < kd) vnext[row<BLOCK>(k)] = w[k];
+        if (k < kd) gst(vnext, row<BLOCK>(k), w[k]);
       }
     }
     total += steps;
@@ -603,9 +622,9 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll 1
     for (int k = 0; k < kd; ++k) {
       const unsigned r = row<BLOCK>(k);
-      double acc = x[r];
-      for (int i = 0; i < steps; ++i) acc += (double)s.yv[i] * (double)basis[(unsigned)i * mp + r];
-      x[r] = acc;
+      double acc = gld(x, r);
+      for (int i = 0; i < steps; ++i) acc += (double)s.yv[i] * (double)gld(basis, (unsigned)i * mp + r);
+      gst(x, r, acc);
     }
     done = !(res > rtol * beta0);
     __syncthreads();
@@ -615,6 +634,8 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 }
 
 template <typename T, int BLOCK, int K>
+// Four waves per SIMD: with about 39 KB of LDS per scenario, four workgroups
+// (four scenarios) share a CU; registers are capped to match.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void nr_kernel(const TxDev<T>* __restrict__ netp, NRLaunch a) {
   constexpr int NW = BLOCK / WAVE;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -637,8 +658,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   // flat start: theta = 0, |V| = set-point at PV and slack, 1 at PQ buses
   for (int i = threadIdx.x; i < n; i += BLOCK) {
-    sc.th[i] = 0.0;
-    sc.vm[i] = i < npq ? 1.0 : VS[ext[i]];
+    gst(sc.th, i, 0.0);
+    gst(sc.vm, i, i < npq ? 1.0 : gld(VS, gld(ext, i)));
   }
   __syncthreads();
 
@@ -662,7 +683,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     // right-hand side -F in place (own rows)
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (k < kd) sc.F[row<BLOCK>(k)] = -sc.F[row<BLOCK>(k)];
+      if (k < kd) gst(sc.F, row<BLOCK>(k), -gld(sc.F, row<BLOCK>(k)));
     bool lin_ok;
     gtotal += gmres_solve<T, BLOCK, K>(apply_j, apply_m, sc.F, sc.dx, basis, mp, kd, R, a.max_restarts,
                                        (T)a.rtol, s, &lin_ok, bm, &work);
@@ -671,8 +692,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     for (int k = 0; k < K; ++k) {
       const int r = (int)row<BLOCK>(k);
       if (k < kd) {
-        if (r < nth) sc.th[r] += sc.dx[r];
-        else if (r < m) sc.vm[r - nth] += sc.dx[r];
+        if (r < nth) gst(sc.th, r, gld(sc.th, r) + gld(sc.dx, r));
+        else if (r < m) gst(sc.vm, r - nth, gld(sc.vm, r - nth) + gld(sc.dx, r));
       }
     }
     work += bm.update();
@@ -682,9 +703,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   double* vout = a.v_out + 2 * (int64_t)b * a.ld;
   for (int i = threadIdx.x; i < n; i += BLOCK) {
-    const int e = ext[i];
-    vout[2 * e] = sc.vre[i];
-    vout[2 * e + 1] = sc.vim[i];
+    const int e = gld(ext, i);
+    gst(vout, 2 * e, gld(sc.vre, i));
+    gst(vout, 2 * e + 1, gld(sc.vim, i));
   }
   if (threadIdx.x == 0) {
     a.newton_iters[b] = newton;
