@@ -215,12 +215,106 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
     return line
 
 
+def bench_adjoint(steps: int, warmup: int) -> dict:
+    """Branch-loss gradient w.r.t. PQ injections (adjoint GMRES) on the 2000-bus grid, batch 256."""
+    import torch
+
+    from paper_2605_14103_amd import pf
+    from workloads import transmission as tx
+    cfg = tx.TX2000_ADJ
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg)
+    ctx = pf.Context(0)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    p, q, vm = dev(batch.p_inj), dev(batch.q_inj), dev(batch.vm_set)
+    B = batch.batch
+    res = net.solve(p, q, vm)
+    loss, g = net.branch_loss(res.v)
+
+    def step():
+        l, gv = net.branch_loss(res.v)
+        return net.adjoint(res.v, gv)
+
+    ms, wall, out = time_steps(step, steps, warmup)
+    ok = int(out[3].sum().item())
+    mean_ms = float(ms.mean())
+    line = {"metric": "adjoint gradients/s (branch loss w.r.t. PQ injections)", "value": ok / (mean_ms * 1e-3),
+            "unit": "gradients/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": mean_ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"tx2000_adj: loss + transposed-Jacobian GMRES, batch {B}", "global_batch": B},
+            "adjoint_gmres_iters_mean": float(out[2].double().mean().item()),
+            "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99))}}
+    net.close()
+    ctx.close()
+    return line
+
+
+def bench_serving(n_requests: int, lam: float) -> dict:
+    """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder)."""
+    from paper_2605_14103_amd import pf, serve
+    from workloads import feeder as fdm
+    from workloads import serving as wsv
+    from workloads import transmission as tx
+    g30 = tx.make_grid(tx.TX30)
+    g2k = tx.make_grid(tx.TX2000)
+    fd = fdm.make_feeder(fdm.FEEDER300)
+    trace = wsv.make_trace(wsv.SERVING, n_requests=n_requests, lam=lam)
+
+    def inputs(r):
+        if r.network == 0:
+            b = tx.make_batch(g30, tx.TX30, batch=r.n_scen, seed=r.seed)
+            return b.p_inj, b.q_inj, b.vm_set
+        if r.network == 1:
+            b = tx.make_batch(g2k, tx.TX2000, batch=r.n_scen, seed=r.seed)
+            return b.p_inj, b.q_inj, b.vm_set
+        b = fdm.make_batch(fd, fdm.FEEDER300, batch=r.n_scen, seed=r.seed)
+        return b.s_wye, b.s_delta
+
+    out = {}
+    for prec in ("fp64", "mixed"):
+        ctx = pf.Context(0)
+        nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
+                pf.DistNetwork.from_feeder(ctx, fd)]
+        budgets = (1 << 30, 24 << 30, 4 << 30)
+        streams = (1, 2, 1)
+        engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec))
+                   for n, b, s in zip(nets, budgets, streams)]
+        # warm-up: one small request per engine (code objects, first launches)
+        warm = [r for r in wsv.make_trace(wsv.SERVING, n_requests=30, lam=lam) if r.n_scen <= 8][:6]
+        serve.replay(engines, warm, inputs, speed=100.0)
+        t = time.perf_counter()
+        st = serve.replay(engines, trace, inputs)
+        summ = st.summary()
+        summ["wall_s"] = time.perf_counter() - t
+        summ["engines"] = [e.info() for e in engines]
+        out[prec] = summ
+        print(f"[serving {prec}] {summ['requests']} requests, {summ['solves_per_s']:.0f} solves/s, "
+              f"p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+        for e in engines:
+            e.close()
+        for n in nets:
+            n.close()
+        ctx.close()
+    r = out["fp64"]
+    return {"metric": METRIC, "value": r["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 1,
+            "warmup": 1, "ms_per_step": r["duration_s"] * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"serving mix: Poisson lambda={lam}/s, {n_requests} requests over tx30, "
+                                   f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8"},
+            "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
+            "fp64": out["fp64"], "mixed": out["mixed"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tx2000", choices=["tx2000", "tx30", "feeder"])
+    ap.add_argument("--workload", default="tx2000", choices=["tx2000", "tx30", "feeder", "adjoint", "serving"])
+    ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
+    ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--cpu-samples", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
     a = ap.parse_args()
@@ -229,12 +323,16 @@ def main() -> int:
         return 2
     workers = min(16, os.cpu_count() or 1)
     cpu = None
-    if not a.no_cpu:
+    if not a.no_cpu and a.workload in ("tx2000", "tx30", "feeder"):
         kind = {"tx2000": "TX2000", "tx30": "TX30", "feeder": "feeder"}[a.workload]
         n_samp = {"tx2000": a.cpu_samples, "tx30": 64, "feeder": 512}[a.workload]
         cpu = cpu_baseline(kind, n_samp, workers)
     if a.workload == "feeder":
         line = bench_feeder(a.steps, a.warmup, cpu)
+    elif a.workload == "adjoint":
+        line = bench_adjoint(a.steps, a.warmup)
+    elif a.workload == "serving":
+        line = bench_serving(a.requests, a.lam)
     else:
         line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
     print(json.dumps(line), flush=True)

@@ -79,6 +79,7 @@ void pf_opts_default(pf_opts* out);
 typedef struct pf_context pf_context;
 typedef struct pf_tx_network pf_tx_network;
 typedef struct pf_dist_network pf_dist_network;
+typedef struct pf_engine pf_engine;
 
 /* ---------------------------------------------------------------- context */
 
@@ -218,6 +219,60 @@ pf_status pf_dist_solve(pf_dist_network* net, const pf_opts* opts, int32_t batch
                         const double* s_wye, const double* s_delta, double* v_out, int32_t* iters,
                         uint8_t* converged, double* final_mismatch, double* sum_abs_change,
                         pf_stream stream);
+
+/* ------------------------------------------------------------- serving */
+
+/* Serving engine: continuous batching of solve requests for one registered
+ * network (the batched solves of Sec. II-A or II-B, served as the requests of
+ * the paper's many-scenario setting arrive).  The engine owns device memory
+ * for max_slots = floor(hbm_bytes / slot_bytes) scenario slots (inputs,
+ * outputs and solver workspace) and n_streams HIP streams, each run by a
+ * worker thread.  Requests wait in FIFO order; whenever a stream is idle the
+ * longest FIFO prefix of waiting requests that fits one contiguous run of
+ * free slots is launched on it as one batched solve, so requests arriving
+ * while others run are admitted as soon as slots and a stream free up and
+ * their kernels overlap with the running ones.  Every scenario's arithmetic is
+ * independent of the other scenarios in its launch, so results are
+ * bit-identical to a solve of the request alone.  Options (precision,
+ * tolerances) are fixed at creation.  An engine is bound to its network and
+ * context: destroying either destroys the engine (pending requests are
+ * dropped).  The engine's calls are thread-safe. */
+
+/* Device bytes of one slot for `opts` (exactly one of tx, dist non-null). */
+pf_status pf_engine_slot_bytes(pf_tx_network* tx, pf_dist_network* dist, const pf_opts* opts,
+                               uint64_t* bytes);
+/* Create an engine over exactly one of tx or dist.  hbm_bytes bounds the slot
+ * memory (PF_INVALID_ARG if below one slot); n_streams in 1..8; opts may be
+ * null.  Errors: PF_INVALID_ARG, PF_BAD_HANDLE, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+pf_status pf_engine_create(pf_context* ctx, pf_tx_network* tx, pf_dist_network* dist, uint64_t hbm_bytes,
+                           int32_t n_streams, const pf_opts* opts, pf_engine** out);
+void pf_engine_destroy(pf_engine* engine);
+/* Queue request `id` (caller-chosen, unique among unfetched requests) of n
+ * scenarios.  Host inputs, copied before return, [n][row]: transmission:
+ * in0 = p_inj, in1 = q_inj, in2 = vm_set (row = n_bus, as in pf_tx_solve);
+ * feeder: in0 = s_wye, in1 = s_delta complex (row = 2 n_node doubles, as in
+ * pf_dist_solve), in2 unused.  Errors: PF_NOT_ADMITTED (n exceeds the
+ * engine's slots), PF_INVALID_ARG (n < 1, duplicate id, null input). */
+pf_status pf_engine_submit(pf_engine* engine, int64_t id, int32_t n, const double* in0, const double* in1,
+                           const double* in2);
+/* Ids of up to max_ids finished requests, oldest first, each reported once;
+ * waits up to timeout_s seconds for the first one (0: do not wait). */
+pf_status pf_engine_poll(pf_engine* engine, int32_t max_ids, int64_t* ids, double timeout_s,
+                         int32_t* count);
+/* Scenario count of an unfetched request.  Errors: PF_INVALID_ARG (unknown id). */
+pf_status pf_engine_request_size(pf_engine* engine, int64_t id, int32_t* n);
+/* Copy a finished request's results to host memory and forget it: v_out
+ * complex [n][row] (row = n_bus or n_node), iters[n] (Newton updates or Z-bus
+ * iterations), converged[n], final_mismatch[n], times[3] (seconds since the
+ * engine was created at submission, launch and completion).  Any output may be
+ * null.  Errors: PF_INVALID_ARG (unknown or unfinished id), PF_HIP_ERROR (the
+ * request's launch failed; the request is forgotten). */
+pf_status pf_engine_fetch(pf_engine* engine, int64_t id, double* v_out, int32_t* iters, uint8_t* converged,
+                          double* final_mismatch, double* times);
+/* Counters (any pointer may be null): slots, bytes per slot, requests waiting,
+ * launches in flight, launches and scenarios completed. */
+pf_status pf_engine_info(pf_engine* engine, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued,
+                         int32_t* in_flight, uint64_t* jobs, uint64_t* scenarios);
 
 #ifdef __cplusplus
 }

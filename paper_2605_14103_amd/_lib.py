@@ -70,6 +70,14 @@ _SIGS = [
     ("pf_dist_network_info", c_int32, [P, I32P, I32P, I32P, I32P]),
     ("pf_dist_solve", c_int32,
      [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, P, P, P, P, P]),
+    ("pf_engine_slot_bytes", c_int32, [P, P, POINTER(PfOpts), POINTER(c_uint64)]),
+    ("pf_engine_create", c_int32, [P, P, P, c_uint64, c_int32, POINTER(PfOpts), POINTER(P)]),
+    ("pf_engine_destroy", None, [P]),
+    ("pf_engine_submit", c_int32, [P, c_int64, c_int32, P, P, P]),
+    ("pf_engine_poll", c_int32, [P, c_int32, P, c_double, I32P]),
+    ("pf_engine_request_size", c_int32, [P, c_int64, I32P]),
+    ("pf_engine_fetch", c_int32, [P, c_int64, P, P, P, P, P]),
+    ("pf_engine_info", c_int32, [P, I32P, POINTER(c_uint64), I32P, I32P, POINTER(c_uint64), POINTER(c_uint64)]),
 ]
 
 _lib = None

@@ -4,6 +4,7 @@
 
 #include "common.hpp"
 #include "dist.hpp"
+#include "engine.hpp"
 #include "tx.hpp"
 
 namespace pfx {
@@ -140,6 +141,7 @@ void pf_context_destroy(pf_context* c) {
   auto* ctx = reinterpret_cast<Context*>(c);
   if (!registry().has(ctx)) return;
   (void)hipSetDevice(ctx->device);
+  destroy_engines_of(ctx, nullptr);
   (void)hipDeviceSynchronize();
   for (void* t : std::set<void*>(ctx->tx_nets)) {
     registry().remove(t);

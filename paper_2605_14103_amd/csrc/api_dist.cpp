@@ -5,6 +5,7 @@
 #include <string>
 
 #include "common.hpp"
+#include "engine.hpp"
 #include "dist.hpp"
 
 using namespace pfx;
@@ -100,8 +101,9 @@ pf_status pf_dist_network_create(pf_context* c, int32_t n_node, int32_t nnz, con
 void pf_dist_network_destroy(pf_dist_network* h) {
   if (!registry().has(h)) return;
   auto* net = reinterpret_cast<DistNetwork*>(h);
-  registry().remove(net);
   Context* ctx = net->ctx;
+  destroy_engines_of(ctx, net);
+  registry().remove(net);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   {
@@ -171,6 +173,7 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     a.st = net->ws_s.as<double>();
     a.active = net->ws_act.as<int32_t>();
     a.count = net->ws_cnt.as<int32_t>();
+    a.count_host = net->count_host;
     run_zbus(*net, mixed, a, reinterpret_cast<hipStream_t>(stream));
   });
 }

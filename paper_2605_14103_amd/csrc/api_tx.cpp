@@ -5,6 +5,7 @@
 #include <string>
 
 #include "common.hpp"
+#include "engine.hpp"
 #include "tx.hpp"
 
 using namespace pfx;
@@ -75,8 +76,9 @@ pf_status pf_tx_network_create(pf_context* c, int32_t n_bus, int32_t nnz, const 
 void pf_tx_network_destroy(pf_tx_network* h) {
   if (!registry().has(h)) return;
   auto* net = reinterpret_cast<TxNetwork*>(h);
-  registry().remove(net);
   Context* ctx = net->ctx;
+  destroy_engines_of(ctx, net);
+  registry().remove(net);
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   {

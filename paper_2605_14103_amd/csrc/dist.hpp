@@ -79,6 +79,7 @@ struct ZbusLaunch {
   double* st;         // [batch][3]: mismatch, sum |v| at the last residual, change of sum |v|
   int32_t* active;    // [rows] 1 while the scenario still iterates
   int32_t* count;     // [max_iter + 1] scenarios still active at each iteration
+  int32_t* count_host;  // pinned host copy of `count`, read back by the host loop
 };
 
 // Runs the whole fixed point on `stream` (host loop over iterations).

@@ -299,12 +299,12 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
     for (int it = 0; it <= a.max_iter; ++it) {
       hipLaunchKernelGGL(zb_residual<T>, dim3(B), dim3(ZB_THREADS), lds, s, d, a, it);
       PFX_HIP(hipGetLastError());
-      PFX_HIP(hipMemcpyAsync(net.count_host + it, a.count + it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      PFX_HIP(hipMemcpyAsync(a.count_host + it, a.count + it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       PFX_HIP(hipEventRecord(ev[it & 1], s));
       // Look one iteration back: once no scenario was active, nothing later can be.
       if (it > 0) {
         PFX_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-        if (net.count_host[it - 1] == 0) break;
+        if (a.count_host[it - 1] == 0) break;
       }
       if (it == a.max_iter) break;
       hipLaunchKernelGGL(zb_gemm<T>, dim3(nt, mt), dim3(256), 0, s, d, W, a);

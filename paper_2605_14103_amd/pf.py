@@ -258,5 +258,84 @@ class DistNetwork:
         return res
 
 
+@dataclass
+class EngineResult:
+    v: np.ndarray            # complex128 (n, row)
+    iters: np.ndarray        # int32 (n,)
+    converged: np.ndarray    # uint8 (n,)
+    mismatch: np.ndarray     # float64 (n,)
+    times: np.ndarray        # float64 (3,): submitted, launched, completed (s since engine creation)
+
+
+class Engine:
+    """Continuous-batching serving engine over one network; see pf_engine_create.
+
+    Host numpy arrays in and out: requests arrive from the host, and the engine
+    stages them through its own pinned buffers into device slots.
+    """
+
+    def __init__(self, network, hbm_bytes: int, n_streams: int = 2, **opts):
+        self.network = network
+        self.kind = "tx" if isinstance(network, TxNetwork) else "dist"
+        self.row = network.n_bus if self.kind == "tx" else network.n_node
+        tx, dist = (network.h, None) if self.kind == "tx" else (None, network.h)
+        self._o = L.opts(**opts)
+        sb = ctypes.c_uint64()
+        L.call("pf_engine_slot_bytes", tx, dist, byref(self._o), byref(sb))
+        self.slot_bytes = int(sb.value)
+        h = c_void_p()
+        L.call("pf_engine_create", network.ctx.h, tx, dist, int(hbm_bytes), int(n_streams), byref(self._o), byref(h))
+        self.h = h
+
+    def submit(self, rid: int, *inputs: np.ndarray) -> None:
+        """Queue request ``rid``: (p, q, vm) float64 (n, n_bus) or (s_wye, s_delta) complex128 (n, n_node)."""
+        want = 3 if self.kind == "tx" else 2
+        if len(inputs) != want:
+            raise ValueError(f"expected {want} input arrays")
+        dt = np.float64 if self.kind == "tx" else np.complex128
+        arrs = [np.ascontiguousarray(a, dtype=dt) for a in inputs]
+        n = int(arrs[0].shape[0])
+        for a in arrs:
+            if a.shape != (n, self.row):
+                raise ValueError(f"inputs must have shape ({n}, {self.row})")
+        ptrs = [_hptr(a) for a in arrs] + [None] * (3 - want)
+        L.call("pf_engine_submit", self.h, int(rid), n, *ptrs)
+
+    def poll(self, max_ids: int = 256, timeout: float = 0.0) -> list[int]:
+        ids = np.zeros(max(1, max_ids), dtype=np.int64)
+        cnt = c_int32()
+        L.call("pf_engine_poll", self.h, int(max_ids), _hptr(ids), float(timeout), byref(cnt))
+        return [int(i) for i in ids[: cnt.value]]
+
+    def fetch(self, rid: int) -> EngineResult:
+        n = c_int32()
+        L.call("pf_engine_request_size", self.h, int(rid), byref(n))
+        n = n.value
+        res = EngineResult(v=np.empty((n, self.row), dtype=np.complex128), iters=np.empty(n, dtype=np.int32),
+                           converged=np.empty(n, dtype=np.uint8), mismatch=np.empty(n),
+                           times=np.empty(3))
+        L.call("pf_engine_fetch", self.h, int(rid), _hptr(res.v), _hptr(res.iters), _hptr(res.converged),
+               _hptr(res.mismatch), _hptr(res.times))
+        return res
+
+    def info(self) -> dict:
+        ms, q, fl = c_int32(), c_int32(), c_int32()
+        sb, jobs, sc = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        L.call("pf_engine_info", self.h, byref(ms), byref(sb), byref(q), byref(fl), byref(jobs), byref(sc))
+        return {"max_slots": ms.value, "slot_bytes": sb.value, "queued": q.value, "in_flight": fl.value,
+                "jobs": jobs.value, "scenarios": sc.value}
+
+    def close(self) -> None:
+        if self.h:
+            L.lib().pf_engine_destroy(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def precision(name: str) -> int:
     return {"fp64": L.PF_FP64, "mixed": L.PF_MIXED}[name]

@@ -1,0 +1,183 @@
+"""Serving engine on the GPU: admission by HBM footprint, continuous batching
+over several streams, and results identical alone and in the mix."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import nr as onr
+from oracle import zbus as ozb
+from tests.gpu_common import angle_err, say, to_dev
+from workloads import feeder as fdm
+from workloads import serving as wsv
+from workloads import transmission as tx
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2605_14103_amd import pf
+    assert torch.cuda.is_available()
+    c = pf.Context(0)
+    yield c
+    c.close()
+
+
+def _collect(eng, ids, timeout=60.0):
+    out = {}
+    deadline = time.time() + timeout
+    while len(out) < len(ids) and time.time() < deadline:
+        for rid in eng.poll(64, 0.01):
+            out[rid] = eng.fetch(rid)
+    assert len(out) == len(ids), f"only {len(out)} of {len(ids)} requests finished"
+    return out
+
+
+def _alone_tx(net, p, q, vm, **opts):
+    import torch
+    r = net.solve(to_dev(p), to_dev(q), to_dev(vm), **opts)
+    torch.cuda.synchronize()
+    return r.v.cpu().numpy(), r.newton_iters.cpu().numpy(), r.converged.cpu().numpy()
+
+
+def _alone_dist(net, sw, sd, **opts):
+    import torch
+    r = net.solve(to_dev(sw), to_dev(sd), **opts)
+    torch.cuda.synchronize()
+    return r.v.cpu().numpy(), r.iters.cpu().numpy(), r.converged.cpu().numpy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tx_alone_equals_mix(ctx, precision):
+    """Requests submitted back to back are packed into shared launches on two
+    streams; every scenario must equal, bit for bit, the same request solved alone."""
+    from paper_2605_14103_amd import pf
+    say("serve tx30", precision)
+    grid = tx.make_grid(tx.TX30)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    prec = pf.precision(precision)
+    sizes = [1, 7, 33, 2, 64, 5, 17, 40, 3, 9, 12, 1]
+    reqs = [tx.make_batch(grid, tx.TX30, batch=n, seed=100 + i) for i, n in enumerate(sizes)]
+    eng = pf.Engine(net, hbm_bytes=1 << 30, n_streams=2, precision=prec)
+    say("engine", eng.info())
+    for i, b in enumerate(reqs):
+        eng.submit(i, b.p_inj, b.q_inj, b.vm_set)
+    got = _collect(eng, list(range(len(reqs))))
+    info = eng.info()
+    say("after", info)
+    assert info["jobs"] < len(reqs), "requests were not batched together"
+    for i, b in enumerate(reqs):
+        v, it, ok = _alone_tx(net, b.p_inj, b.q_inj, b.vm_set, precision=prec)
+        r = got[i]
+        assert r.converged.all() and ok.all()
+        assert np.array_equal(r.v.view(np.float64), v.view(np.float64)), f"request {i} differs from alone"
+        assert np.array_equal(r.iters, it)
+        assert r.mismatch.max() <= 1e-8
+        assert r.times[0] <= r.times[1] <= r.times[2]
+    # and the mix against the oracle for a few requests
+    for i in (1, 4):
+        V, _, ok, _ = onr.nr_solve_batch(grid, reqs[i])
+        da, dm = angle_err(got[i].v, V)
+        assert ok.all() and da <= 1e-6 and dm <= 1e-6
+    eng.close()
+    net.close()
+
+
+def test_feeder_alone_equals_mix(ctx):
+    from paper_2605_14103_amd import pf
+    say("serve feeder40")
+    cfg = fdm.FeederConfig("feeder40", n_bus=40, max_depth=25, batch=1, seed=41)
+    fd = fdm.make_feeder(cfg)
+    net = pf.DistNetwork.from_feeder(ctx, fd)
+    sizes = [3, 130, 1, 64, 200, 7, 129, 2]
+    reqs = [fdm.make_batch(fd, cfg, batch=n, seed=500 + i) for i, n in enumerate(sizes)]
+    eng = pf.Engine(net, hbm_bytes=64 << 20, n_streams=2)
+    say("engine", eng.info())
+    for i, b in enumerate(reqs):
+        eng.submit(i, b.s_wye, b.s_delta)
+    got = _collect(eng, list(range(len(reqs))))
+    say("after", eng.info())
+    for i, b in enumerate(reqs):
+        v, it, ok = _alone_dist(net, b.s_wye, b.s_delta)
+        r = got[i]
+        assert r.converged.all() and ok.all()
+        assert np.array_equal(r.v.view(np.float64), v.view(np.float64)), f"request {i} differs from alone"
+        assert np.array_equal(r.iters, it)
+    ref = ozb.zbus_solve(fd, reqs[0])
+    da, dm = angle_err(got[0].v, ref.v)
+    assert da <= 1e-6 and dm <= 1e-6
+    eng.close()
+    net.close()
+
+
+def test_admission_limits_and_lifetime(ctx):
+    from paper_2605_14103_amd import _lib as L
+    from paper_2605_14103_amd import pf
+    grid = tx.make_grid(tx.TX30)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    probe = pf.Engine(net, hbm_bytes=1 << 24, n_streams=1)
+    slot = probe.slot_bytes
+    probe.close()
+    with pytest.raises(L.PfError) as e:
+        pf.Engine(net, hbm_bytes=slot - 1)
+    assert e.value.status == L.PF_INVALID_ARG
+    eng = pf.Engine(net, hbm_bytes=4 * slot, n_streams=1)
+    assert eng.info()["max_slots"] == 4
+    b = tx.make_batch(grid, tx.TX30, batch=5, seed=1)
+    with pytest.raises(L.PfError) as e:
+        eng.submit(0, b.p_inj, b.q_inj, b.vm_set)
+    assert e.value.status == L.PF_NOT_ADMITTED
+    # three requests of 3 slots on a 4-slot engine run one after another
+    for i in range(3):
+        eng.submit(10 + i, b.p_inj[:3], b.q_inj[:3], b.vm_set[:3])
+    got = _collect(eng, [10, 11, 12])
+    assert all(r.converged.all() for r in got.values())
+    assert eng.info()["jobs"] == 3
+    eng.submit(20, b.p_inj[:1], b.q_inj[:1], b.vm_set[:1])
+    with pytest.raises(L.PfError) as e:
+        eng.submit(20, b.p_inj[:1], b.q_inj[:1], b.vm_set[:1])
+    assert e.value.status == L.PF_INVALID_ARG
+    _collect(eng, [20])
+    # destroying the network takes the engine with it
+    net.close()
+    with pytest.raises(L.PfError) as e:
+        eng.info()
+    assert e.value.status == L.PF_BAD_HANDLE
+    eng.h = None
+
+
+def test_short_trace_replay(ctx):
+    """A compressed Poisson trace over two grids and a feeder; everything converges."""
+    from paper_2605_14103_amd import pf, serve
+    say("serve replay")
+    g30 = tx.make_grid(tx.TX30)
+    cfg_f = fdm.FeederConfig("feeder40", n_bus=40, max_depth=25, batch=1, seed=41)
+    fd = fdm.make_feeder(cfg_f)
+    cfg_b = tx.TxConfig("tx200", n_bus=200, n_pv=30, n_branch=260, batch=1, seed=200,
+                        perturbation="uniform", spread=0.2)
+    g200 = tx.make_grid(cfg_b)
+    nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g200), pf.DistNetwork.from_feeder(ctx, fd)]
+    engines = [pf.Engine(n, hbm_bytes=256 << 20, n_streams=s) for n, s in zip(nets, (1, 2, 1))]
+    trace = wsv.make_trace(wsv.ServingConfig(lam=4000.0, n_requests=60, max_scen=64, n_networks=3, seed=11))
+
+    def inputs(r):
+        if r.network == 0:
+            b = tx.make_batch(g30, tx.TX30, batch=r.n_scen, seed=r.seed)
+            return b.p_inj, b.q_inj, b.vm_set
+        if r.network == 1:
+            b = tx.make_batch(g200, cfg_b, batch=r.n_scen, seed=r.seed)
+            return b.p_inj, b.q_inj, b.vm_set
+        b = fdm.make_batch(fd, cfg_f, batch=r.n_scen, seed=r.seed)
+        return b.s_wye, b.s_delta
+
+    st = serve.replay(engines, trace, inputs, timeout_s=60)
+    summ = st.summary()
+    say("replay", {k: v for k, v in summ.items() if k != "per_network"})
+    assert not st.failed
+    assert summ["converged"] == summ["scenarios"] == sum(r.n_scen for r in trace)
+    for e in engines:
+        e.close()
+    for n in nets:
+        n.close()

@@ -209,3 +209,52 @@ def test_adjoint_matches_dense_adjoint(ctx, cfg, cols):
         say(f"adjoint {cfg.name} scenario {c}: rel err {err:.2e}, gmres {int(its[c])}")
         assert err <= 1e-8
     net.close()
+
+
+def test_autograd_matches_finite_differences(ctx):
+    """Gradient of a torch loss on the solved voltages through the adjoint, against
+    central differences of the oracle's solves (h = 1e-6, solves to 1e-12)."""
+    import torch
+    from oracle import nr as onr
+    from paper_2605_14103_amd import autograd, pf
+    grid = tx.make_grid(tx.TX30)
+    batch = tx.make_batch(grid, tx.TX30, batch=2)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    p = to_dev(batch.p_inj).requires_grad_(True)
+    q = to_dev(batch.q_inj).requires_grad_(True)
+    vm = to_dev(batch.vm_set)
+    v, conv = autograd.solve(net, p, q, vm, tol=1e-12)
+    f = torch.from_numpy(grid.f.astype(np.int64)).cuda()
+    t = torch.from_numpy(grid.t.astype(np.int64)).cuda()
+    ys = torch.from_numpy(1.0 / (grid.r + 1j * grid.x)).cuda()
+    yff = ys + 0.5j * torch.from_numpy(grid.b).cuda()
+    i_f = yff * v[:, f] - ys * v[:, t]
+    loss = (i_f.abs() ** 2).sum()
+    loss.backward()
+    gp = p.grad.cpu().numpy()
+    gq = q.grad.cpu().numpy()
+    Y = onr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
+
+    def L(pp, qq, c):
+        r = onr.nr_solve(Y, grid.bus_type, pp, qq, batch.vm_set[c], tol=1e-13)
+        vv = r.V
+        return float(np.sum(np.abs((1 / (grid.r + 1j * grid.x) + 0.5j * grid.b) * vv[grid.f]
+                                   - (1 / (grid.r + 1j * grid.x)) * vv[grid.t]) ** 2))
+
+    h = 1e-6
+    theta = np.flatnonzero(grid.bus_type != tx.SLACK)
+    pq = np.flatnonzero(grid.bus_type == tx.PQ)
+    scale = max(np.abs(gp).max(), np.abs(gq).max())
+    for c in range(2):
+        for k in theta[::5]:
+            e = np.zeros(grid.n_bus)
+            e[k] = h
+            fd = (L(batch.p_inj[c] + e, batch.q_inj[c], c) - L(batch.p_inj[c] - e, batch.q_inj[c], c)) / (2 * h)
+            assert abs(fd - gp[c, k]) <= 1e-5 * scale
+        for k in pq[::5]:
+            e = np.zeros(grid.n_bus)
+            e[k] = h
+            fd = (L(batch.p_inj[c], batch.q_inj[c] + e, c) - L(batch.p_inj[c], batch.q_inj[c] - e, c)) / (2 * h)
+            assert abs(fd - gq[c, k]) <= 1e-5 * scale
+        assert gp[c, grid.slack] == 0 and np.all(gq[c, grid.bus_type != tx.PQ] == 0)
+    net.close()
