@@ -70,7 +70,8 @@ typedef struct pf_opts {
   double eps;                 /* diagonal regularisation of B' and B'' (Sec. II-A), default 1e-8 */
   int32_t precond_block;      /* 0: exact (B'+eps I)^-1, (B''+eps I)^-1 (default);
                                  k > 0: block-Jacobi over diagonal blocks of k buses */
-  int32_t factor_max_levels;  /* sparse elimination levels before the dense core, default 8 */
+  int32_t factor_max_levels;  /* at most this many sparse elimination levels before the dense
+                                 core; the set-up picks the cheapest split, default 8 */
   int32_t factor_max_core;    /* largest dense Schur core, default 384 */
 } pf_opts;
 
@@ -118,7 +119,8 @@ pf_status pf_tx_ybus_from_branches(int32_t n_bus, int32_t n_branch, const int32_
  * The index sets are Theta = PV u PQ and Q = PQ (Sec. II-A); B' and B'' are
  * -Im(Ybus) on Theta x Theta and Q x Q, G = -Re(Ybus) on Q x Theta (eq. (7)).
  * Their regularised inverses are factorised here, once (Sec. II-A: the
- * inverses are precomputed).  setup_opts may be null (defaults).
+ * inverses are precomputed).  setup_opts may be null (defaults).  Networks of
+ * up to 8192 buses are supported.
  * Errors: PF_INVALID_ARG, PF_SINGULAR_SETUP, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_tx_network_create(pf_context* ctx, int32_t n_bus, int32_t nnz, const int32_t* row_ptr,
                                const int32_t* col_idx, const double* y_re, const double* y_im,
@@ -126,8 +128,9 @@ pf_status pf_tx_network_create(pf_context* ctx, int32_t n_bus, int32_t nnz, cons
                                const int32_t* br_t, const double* br_r, const double* br_x,
                                const double* br_b, const pf_opts* setup_opts, pf_tx_network** out);
 void pf_tx_network_destroy(pf_tx_network* net);
-/* Sizes: n_bus, |Theta|, |Q|, nnz(Ybus), sparse factor nonzeros and dense core
- * sizes of the B' and B'' inverses (any pointer may be null). */
+/* Sizes: n_bus, |Theta|, |Q|, nnz(Ybus), stored sparse entries of the
+ * explicit (B' + eps I)^-1 and (B'' + eps I)^-1 passes, and the dense core
+ * sizes of the two inverses (any pointer may be null). */
 pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* n_theta,
                              int32_t* n_q, int32_t* nnz, int32_t* factor_nnz, int32_t* core_bp,
                              int32_t* core_bpp);

@@ -96,7 +96,7 @@ pf_status pf_tx_network_info(const pf_tx_network* h, int32_t* n_bus, int32_t* n_
     if (n_theta) *n_theta = net->nth;
     if (n_q) *n_q = net->npq;
     if (nnz) *nnz = net->nnz;
-    if (factor_nnz) *factor_nnz = net->bp.host.factor_nnz + net->bpp.host.factor_nnz;
+    if (factor_nnz) *factor_nnz = (int32_t)(net->bp.host.entries() + net->bpp.host.entries());
     if (core_bp) *core_bp = net->bp.host.k;
     if (core_bpp) *core_bpp = net->bpp.host.k;
   });

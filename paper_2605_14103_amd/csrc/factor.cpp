@@ -296,3 +296,128 @@ std::vector<double> hybrid_solve(const HybridFactor& F, const std::vector<double
 }
 
 }  // namespace pfx
+
+namespace pfx {
+
+long ExplicitFactor::entries() const {
+  long e = 0;
+  for (const auto& r : e1) e += (long)r.size();
+  for (const auto& r : e3) e += (long)r.size();
+  return e;
+}
+
+ExplicitFactor explicit_form(const HybridFactor& F) {
+  const int N = F.N, c = F.c, k = F.k;
+  ExplicitFactor E;
+  E.N = N;
+  E.c = c;
+  E.k = k;
+  E.perm = F.perm;
+  E.pinv = F.pinv;
+  E.Sinv = F.Sinv;
+  // Column lists of L over prefix columns: lc[j] = rows i > j with L[i][j] != 0.
+  std::vector<std::vector<std::pair<int, double>>> lc(c);
+  for (int i = 0; i < N; ++i)
+    for (int p = F.L_ptr[i]; p < F.L_ptr[i + 1]; ++p) lc[F.L_col[p]].push_back({i, F.L_val[p]});
+  E.e1.assign(N, {});
+  E.e3.assign(N, {});
+  std::vector<int> mark(N, -1);
+  std::vector<double> y(N, 0.0);
+  std::vector<int> reach;
+  for (int j = 0; j < c; ++j) {
+    // nonzero pattern of L^-1 e_j: positions reachable from j through L
+    reach.clear();
+    reach.push_back(j);
+    mark[j] = j;
+    for (size_t q = 0; q < reach.size(); ++q) {
+      const int u = reach[q];
+      if (u >= c) continue;
+      for (auto [v, l] : lc[u])
+        if (mark[v] != j) {
+          mark[v] = j;
+          reach.push_back(v);
+        }
+    }
+    std::sort(reach.begin(), reach.end());
+    // forward substitution in increasing position order (L is lower triangular)
+    y[j] = 1.0;
+    for (int u : reach) {
+      if (u == j) continue;
+      double a = 0.0;
+      for (int p = F.L_ptr[u]; p < F.L_ptr[u + 1]; ++p) a -= F.L_val[p] * y[F.L_col[p]];
+      y[u] = a;
+    }
+    for (int u : reach) {
+      if (y[u] != 0.0) {
+        E.e3[j].push_back({u, y[u]});                                  // column j of L^-1
+        E.e1[u].push_back({j, u < c ? F.dinv[u] * y[u] : y[u]});       // row u of Dt'^-1 L^-1
+      }
+    }
+    for (int u : reach) y[u] = 0.0;   // positions outside the next reach must read as zero
+  }
+  for (int r = c; r < N; ++r) {
+    E.e1[r].push_back({r, 1.0});
+    E.e3[r].push_back({r, 1.0});
+  }
+  for (auto& r : E.e1) std::sort(r.begin(), r.end());
+  return E;
+}
+
+std::vector<double> explicit_solve(const ExplicitFactor& E, const std::vector<double>& b) {
+  const int N = E.N, c = E.c, k = E.k;
+  std::vector<double> bf(N), u(N), x(N);
+  for (int r = 0; r < N; ++r) bf[E.pinv[r]] = b[r];
+  for (int r = 0; r < N; ++r) {
+    double a = 0.0;
+    for (auto [j, v] : E.e1[r]) a += v * bf[j];
+    u[r] = a;
+  }
+  for (int i = 0; i < k; ++i) {
+    double a = 0.0;
+    for (int l = 0; l < k; ++l) a += E.Sinv[(size_t)l * k + i] * u[c + l];
+    x[c + i] = a;
+  }
+  for (int r = 0; r < c; ++r) x[r] = u[r];
+  std::vector<double> out(N);
+  for (int p = 0; p < N; ++p) {
+    double a = 0.0;
+    for (auto [j, v] : E.e3[p]) a += v * x[j];
+    out[E.perm[p]] = a;
+  }
+  return out;
+}
+
+ExplicitFactor explicit_factor(const SparseSym& A, int max_levels, int max_core, int block) {
+  ExplicitFactor best;
+  double best_cost = -1.0;
+  std::string last_error;
+  for (int lv = 1; lv <= std::max(1, max_levels); ++lv) {
+    HybridFactor F;
+    try {
+      F = hybrid_factor(A, lv, max_core);
+    } catch (const PfError& e) {
+      last_error = e.what();
+      continue;
+    }
+    ExplicitFactor E = explicit_form(F);
+    // Sparse entries padded to slices of 64 rows sorted by length, as laid out on the device.
+    auto padded = [](const std::vector<std::vector<std::pair<int, double>>>& rows) {
+      std::vector<int> len;
+      for (const auto& r : rows) len.push_back((int)r.size());
+      std::sort(len.begin(), len.end(), std::greater<int>());
+      long pad = 0;
+      for (size_t s = 0; s < len.size(); s += 64) pad += 64L * len[s];
+      return pad;
+    };
+    const double cost = (double)(padded(E.e1) + padded(E.e3)) / block + (double)E.k * E.k / std::max(1, std::min(E.k, block));
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = std::move(E);
+    }
+    if (F.n_fwd_levels() < lv) break;   // more levels would not change the split
+  }
+  if (best_cost < 0) fail(PF_SINGULAR_SETUP, last_error.empty() ? "factorisation failed" : last_error);
+  return best;
+}
+
+}  // namespace pfx

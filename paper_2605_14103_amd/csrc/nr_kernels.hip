@@ -1,31 +1,33 @@
 // Batched Newton-Raphson power flow for meshed grids (Sec. II-A), one
 // workgroup per scenario, and its adjoint.
 //
-// A workgroup owns one scenario for its whole solve: every vector of length n
-// (buses) or m = |Theta| + |Q| (Newton state) is split over the workgroup's
-// threads by rows (thread t owns rows t, t + BLOCK, ...), so per-scenario dot
-// products and norms are workgroup reductions and no grid-wide
+// A workgroup owns one scenario for its whole solve.  Thread t owns internal
+// buses i = t + k BLOCK (k < KB) and, for each, both Newton-state entries of
+// that bus (angle and magnitude; see tx.hpp): vectors of the Newton space live
+// in registers as w[k] (angle of bus slot k) and w[KB + k] (magnitude), and in
+// HBM as two planes of nbp entries, so every streaming access is coalesced and
+// per-scenario dot products are workgroup reductions.  No grid-wide
 // synchronisation is ever needed.  Per-scenario data:
-//   * LDS (about 39 KB at 2000 buses in FP64, so four workgroups share a CU):
-//     the vector being gathered (V for Ybus V, the direction of the
-//     Jacobian-vector product, the preconditioner's work vector), the packed
-//     Hessenberg matrix and the Givens rotations;
-//   * registers: the current Krylov vector w;
-//   * HBM (scenario-major workspace): theta, |V|, 1/|V|, V, I, F, the Newton step
-//     and the Krylov basis, always accessed at the thread's own rows, so
-//     consecutive lanes touch consecutive addresses.
-// The shared network data (Ybus, factors of B' and B'') is read through the
-// caches by every workgroup; its descriptor sits in device memory.
+//   * LDS (about 40 KB at 2000 buses in FP64, so four workgroups share a CU):
+//     the vector being gathered (V for Ybus V, dV for the Jacobian-vector
+//     product, the preconditioner's right-hand sides), reduction partials, the
+//     packed Hessenberg matrix and the Givens rotations;
+//   * HBM (scenario-major workspace): theta, |V|, 1/|V|, V, I, P, Q, F, the
+//     Newton step and the Krylov basis.
+// Network data (sliced Ybus, G, the explicit factors of B' and B'') is shared
+// by all workgroups and read through the caches; it is never written during a
+// launch, so it is read through the constant address space.
 //
 // Steps per Newton iteration (eqs. (1)-(3), (7)-(9)):
 //   mismatch  V = |V| e^{j theta}, I = Ybus V, S = V conj(I),
 //             F = [Re S - P on Theta ; Im S - Q on Q], max |F|
 //   GMRES     left-preconditioned restarted GMRES on J dx = -F with
 //             Jacobian-vector products dS = dV conj(I) + V conj(Ybus dV),
-//             dV = V (j dtheta + d|V| / |V|), the preconditioner applied by
-//             forward block substitution, classical Gram-Schmidt with a second
-//             pass whenever the first cancels more than 1 - 1/sqrt(2) of the
-//             norm (Kahan-Parlett), Givens rotations on the Hessenberg matrix
+//             dV = V (j dtheta + d|V| / |V|), the preconditioner applied by the
+//             forward block substitution of eqs. (8)-(9) with explicit factor
+//             passes, classical Gram-Schmidt with a second pass whenever the
+//             first cancels more than half of the squared norm (Kahan-Parlett),
+//             Givens rotations on the Hessenberg matrix
 //   update    theta += dx_theta, |V| += dx_|V|   (FP64)
 #include <hip/hip_runtime.h>
 
@@ -48,6 +50,43 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Sum over the 64 lanes of a wave with DPP row operations (no LDS traffic):
+// quad swaps, half-row and row mirrors, then the row broadcasts; the total
+// ends in lane 63 and is returned to every lane through a scalar register.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ float wave_total(float v) {
+  v += dpp_f<0xB1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xf>(v);  // row_half_mirror
+  v += dpp_f<0x140, 0xf>(v);  // row_mirror
+  v += dpp_f<0x142, 0xa>(v);  // row_bcast15 into rows 1 and 3
+  v += dpp_f<0x143, 0xc>(v);  // row_bcast31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_d<0xB1, 0xf>(v);
+  v += dpp_d<0x4E, 0xf>(v);
+  v += dpp_d<0x141, 0xf>(v);
+  v += dpp_d<0x140, 0xf>(v);
+  v += dpp_d<0x142, 0xa>(v);
+  v += dpp_d<0x143, 0xc>(v);
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 // max that propagates NaN
 __device__ __forceinline__ double nanmax(double a, double b) {
   if (a != a) return a;
@@ -61,63 +100,56 @@ __device__ __forceinline__ double wave_nanmax(double v) {
   return v;
 }
 
-// Workgroup sum; every thread gets the same result.  Ends with a barrier so
-// `red` can be reused right away.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)); }
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+// The network descriptor is re-read at the start of each phase: hiding the
+// pointer's value from the optimiser keeps the descriptor's ~50 fields from
+// being held in registers across the whole kernel, and reading it through the
+// constant address space keeps the reads scalar (only the fields a phase uses
+// are loaded).
+template <typename P>
+__device__ __forceinline__ P load_desc(const P* p) {
+  static_assert(sizeof(P) % 8 == 0, "descriptor size");
+  asm volatile("" : "+s"(p));
+  typedef __attribute__((address_space(4))) const unsigned long long CU;
+  unsigned long long words[sizeof(P) / 8];
+#pragma unroll
+  for (unsigned i = 0; i < sizeof(P) / 8; ++i) words[i] = ((CU*)p)[i];
+  P out;
+  __builtin_memcpy(&out, words, sizeof(P));
+  return out;
+}
+
+// Workgroup sum into every thread.  `part` (NW entries) must not be written
+// again before the next barrier: callers alternate between two buffers.
 template <typename T, int BLOCK>
-__device__ T block_sum(T v, T* red) {
+__device__ T block_sum(T v, T* part) {
   constexpr int NW = BLOCK / WAVE;
-  v = wave_sum(v);
-  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  v = wave_total(v);
+  if (lane_id() == 0) part[wave_id()] = v;
   __syncthreads();
   T s = 0;
 #pragma unroll
-  for (int i = 0; i < NW; ++i) s += red[i];
-  __syncthreads();
+  for (int i = 0; i < NW; ++i) s += part[i];
   return s;
 }
 
 template <int BLOCK>
-__device__ double block_nanmax(double v, double* red) {
+__device__ double block_nanmax(double v, double* part) {
   constexpr int NW = BLOCK / WAVE;
   v = wave_nanmax(v);
-  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
+  if (lane_id() == 0) part[wave_id()] = v;
   __syncthreads();
-  double s = red[0];
+  double s = part[0];
 #pragma unroll
-  for (int i = 1; i < NW; ++i) s = nanmax(s, red[i]);
-  __syncthreads();
+  for (int i = 1; i < NW; ++i) s = nanmax(s, part[i]);
   return s;
 }
 
-// Runtime-indexed access to a register array through a select chain, so that
-// loops with heavy bodies can stay rolled while the array stays in registers.
-template <typename T, int K>
-__device__ __forceinline__ T rget(const T (&w)[K], int k) {
-  T v = w[0];
-#pragma unroll
-  for (int q = 1; q < K; ++q)
-    if (q == k) v = w[q];
-  return v;
-}
-
-template <typename T, int K>
-__device__ __forceinline__ void rset(T (&w)[K], int k, T v) {
-#pragma unroll
-  for (int q = 0; q < K; ++q)
-    if (q == k) w[q] = v;
-}
-
-// Row k of thread t is t + k BLOCK.  Per-scenario state vectors are padded to
-// kd BLOCK rows (zeros past m), so the streaming loops carry no row guards.
-template <int BLOCK>
-__device__ __forceinline__ unsigned row(int k) {
-  return threadIdx.x + (unsigned)k * BLOCK;
-}
-
-// Global-memory element access by a 32-bit index from a base pointer that is
-// uniform across the workgroup: the byte offset stays 32-bit and the pointer
-// is tagged global, so the scalar-base plus vector-offset form is used instead
-// of a 64-bit address per element.
+// Per-scenario data: element access by a 32-bit index from a base pointer that
+// is uniform across the workgroup (global address space, scalar base plus a
+// 32-bit vector offset).
 template <typename T>
 __device__ __forceinline__ T gld(const T* base, unsigned i) {
   typedef __attribute__((address_space(1))) const char GC;
@@ -132,31 +164,105 @@ __device__ __forceinline__ void gst(T* base, unsigned i, T v) {
   *(GT*)((GC*)base + i * (unsigned)sizeof(T)) = v;
 }
 
+// Network data: read-only for the whole launch, so it is read through the
+// constant address space (scalar loads at uniform indexes, free scheduling).
+template <typename T>
+__device__ __forceinline__ T cld(const T* base, unsigned i) {
+  typedef __attribute__((address_space(4))) const char CC;
+  typedef __attribute__((address_space(4))) const T CT;
+  return *(CT*)((CC*)base + i * (unsigned)sizeof(T));
+}
+
+// complex entries: one 16- (or 8-) byte load of the native two-element vector
+__device__ __forceinline__ double2 cld(const double2* base, unsigned i) {
+  typedef double __attribute__((ext_vector_type(2))) D2;
+  typedef __attribute__((address_space(4))) const char CC;
+  typedef __attribute__((address_space(4))) const D2 CT;
+  const D2 v = *(CT*)((CC*)base + i * 16u);
+  double2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+__device__ __forceinline__ float2 cld(const float2* base, unsigned i) {
+  typedef float __attribute__((ext_vector_type(2))) F2;
+  typedef __attribute__((address_space(4))) const char CC;
+  typedef __attribute__((address_space(4))) const F2 CT;
+  const F2 v = *(CT*)((CC*)base + i * 8u);
+  float2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
+// Compiler-only fence between the bus slots of an unrolled loop: keeps the
+// loads of later slots from being hoisted above earlier ones, which would hold
+// every slot's operands in registers at once.
+__device__ __forceinline__ void slot_fence() { asm volatile("" ::: "memory"); }
+
+// Forces a value to be computed at this point (it cannot be sunk below), so a
+// slot's result does not keep its operands alive through the later slots.
+template <typename T>
+__device__ __forceinline__ void settle(T& x) {
+  asm volatile("" : "+v"(x));
+}
+
+__device__ __forceinline__ int4 cld(const int4* base, unsigned i) {
+  typedef int __attribute__((ext_vector_type(4))) I4;
+  typedef __attribute__((address_space(4))) const char CC;
+  typedef __attribute__((address_space(4))) const I4 CT;
+  const I4 v = *(CT*)((CC*)base + i * 16u);
+  int4 r;
+  r.x = v.x;
+  r.y = v.y;
+  r.z = v.z;
+  r.w = v.w;
+  return r;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ unsigned row(int k) {
+  return threadIdx.x + (unsigned)k * BLOCK;
+}
+
 struct NrLayout {
-  int xs, tmp, red, h1, h2, H, cs, sn, g, y, misc, total;
+  int xs, tmp, red, H, cs, sn, gres, gfin, y, total;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// Column j of the packed Hessenberg matrix holds rows 0..j+1 at offset j(j+3)/2.
-__host__ __device__ inline int hcol(int j) { return j * (j + 3) / 2; }
+// Column j of the packed Hessenberg matrix holds rows 0..j at offset j(j+1)/2.
+__host__ __device__ inline int hcol(int j) { return j * (j + 1) / 2; }
 
-__host__ __device__ inline NrLayout nr_layout(int n, int m, int kmax, int R, int NW, int ts) {
+__host__ __device__ inline NrLayout nr_layout(int nbp, int nth, int npq, int kmax, int R, int NW, int ts) {
   NrLayout L;
   int o = 0;
-  const int xs_bytes = m * ts > 2 * n * 8 ? m * ts : 2 * n * 8;
-  L.xs = o;   o += align16(xs_bytes);
-  L.tmp = o;  o += align16((kmax > 0 ? kmax : 1) * ts);
-  const int red_bytes = (R + 2) * NW * ts > NW * 8 ? (R + 2) * NW * ts : NW * 8;
+  int xs_bytes = 2 * nbp * 8;                          // V (FP64 pairs) in the mismatch
+  if (2 * nbp * ts > xs_bytes) xs_bytes = 2 * nbp * ts;  // dV pairs in the Jacobian-vector product
+  // the preconditioner's two right-hand sides and pass buffers: [0, 2 nth) and [nth, nth + npq)
+  if (2 * nth * ts > xs_bytes) xs_bytes = 2 * nth * ts;
+  if ((nth + npq) * ts > xs_bytes) xs_bytes = (nth + npq) * ts;
+  L.xs = o;
+  o += align16(xs_bytes);
+  // Reduction partials, double-buffered.  The preconditioner's dense-core
+  // right-hand side lives there too when it fits: no partial is pending while
+  // the preconditioner runs (each phase in between ends with a barrier).
+  const int red_bytes = 2 * (R + 2) * NW * 8;
   L.red = o;  o += align16(red_bytes);
-  L.h1 = o;   o += align16((R + 2) * ts);
-  L.h2 = o;   o += align16((R + 2) * ts);
+  const int tmp_bytes = (kmax > 0 ? kmax : 1) * ts;
+  if (tmp_bytes <= red_bytes) {
+    L.tmp = L.red;
+  } else {
+    L.tmp = o;
+    o += align16(tmp_bytes);
+  }
   L.H = o;    o += align16(hcol(R) * ts);
   L.cs = o;   o += align16(R * ts);
   L.sn = o;   o += align16(R * ts);
-  L.g = o;    o += align16((R + 1) * ts);
+  L.gres = o; o += align16((R + 1) * ts);
+  L.gfin = o; o += align16(R * ts);
   L.y = o;    o += align16(R * ts);
-  L.misc = o; o += 64;
   L.total = o;
   return L;
 }
@@ -164,322 +270,394 @@ __host__ __device__ inline NrLayout nr_layout(int n, int m, int kmax, int R, int
 template <typename T>
 struct Smem {
   T* xs;
-  double* vs;
+  double2* vs;
   T* tmp;
   T* red;
   double* redd;
-  T* h1;
-  T* h2;
   T* H;
   T* cs;
   T* sn;
-  T* g;
+  T* gres;
+  T* gfin;
   T* yv;
-  T* misc;
 };
 
 template <typename T>
 __device__ Smem<T> carve(unsigned char* smem, const NrLayout& L) {
   Smem<T> s;
   s.xs = reinterpret_cast<T*>(smem + L.xs);
-  s.vs = reinterpret_cast<double*>(smem + L.xs);
+  s.vs = reinterpret_cast<double2*>(smem + L.xs);
   s.tmp = reinterpret_cast<T*>(smem + L.tmp);
   s.red = reinterpret_cast<T*>(smem + L.red);
   s.redd = reinterpret_cast<double*>(smem + L.red);
-  s.h1 = reinterpret_cast<T*>(smem + L.h1);
-  s.h2 = reinterpret_cast<T*>(smem + L.h2);
   s.H = reinterpret_cast<T*>(smem + L.H);
   s.cs = reinterpret_cast<T*>(smem + L.cs);
   s.sn = reinterpret_cast<T*>(smem + L.sn);
-  s.g = reinterpret_cast<T*>(smem + L.g);
+  s.gres = reinterpret_cast<T*>(smem + L.gres);
+  s.gfin = reinterpret_cast<T*>(smem + L.gfin);
   s.yv = reinterpret_cast<T*>(smem + L.y);
-  s.misc = reinterpret_cast<T*>(smem + L.misc);
   return s;
 }
 
-// ---------------------------------------------------------------------------
-// Solve (B + eps I) x = b in place for the vector held in LDS in factor order
-// (see factor.hpp).  The factor is A = L D L^T with unit lower L over the
-// sparse prefix and the explicit inverse of the Schur complement S over the
-// dense core:
-//   y1 = L11^-1 b1 (levels), t = b2 - L21 y1, x2 = S^-1 t, w1 = D11^-1 y1,
-//   x1 = L11^-T (w1 - L21^T x2) (levels, reverse order).
-// Ends with a barrier.
-template <typename T, int BLOCK>
-__device__ void spd_apply(const SpdDev<T>& f, T* xs, T* tmp) {
-  for (int l = 0; l < f.nfl; ++l) {
-    const int s = gld(f.f_lev, l), e = gld(f.f_lev, l + 1);
-    for (int q = s + (int)threadIdx.x; q < e; q += BLOCK) {
-      const int i = gld(f.f_rows, q);
-      T a = xs[i];
-      const int pe = gld(f.L_ptr, i + 1);
-      for (int p = gld(f.L_ptr, i); p < pe; ++p) a -= gld(f.L_val, p) * xs[gld(f.L_col, p)];
-      xs[i] = a;
-    }
-    __syncthreads();
+// Raw buffer access to per-scenario memory: a buffer resource holds the base
+// address (scalar registers), each lane supplies a 32-bit byte offset and the
+// array/slot offset is a uniform (usually constant) scalar offset.  One lane
+// offset then serves every array and every bus slot, so addresses take no
+// vector registers beyond it.
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void* base) {
+  return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000)};
+}
+
+template <typename T>
+__device__ __forceinline__ T bld(const Buf& b, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ double bld<double>(const Buf& b, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0);
+  double d;
+  __builtin_memcpy(&d, &v, 8);
+  return d;
+}
+template <>
+__device__ __forceinline__ float bld<float>(const Buf& b, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0);
+  float f;
+  __builtin_memcpy(&f, &v, 4);
+  return f;
+}
+
+__device__ __forceinline__ void bst(const Buf& b, double x, unsigned voff, unsigned soff) {
+  decltype(__builtin_amdgcn_raw_buffer_load_b64(b.r, 0, 0, 0)) v;
+  __builtin_memcpy(&v, &x, 8);
+  __builtin_amdgcn_raw_buffer_store_b64(v, b.r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void bst(const Buf& b, float x, unsigned voff, unsigned soff) {
+  decltype(__builtin_amdgcn_raw_buffer_load_b32(b.r, 0, 0, 0)) v;
+  __builtin_memcpy(&v, &x, 4);
+  __builtin_amdgcn_raw_buffer_store_b32(v, b.r, (int)voff, (int)soff, 0);
+}
+
+// One scenario's FP64 workspace: 13 planes of NBP = KB BLOCK doubles.  Plane
+// F and DX span two planes each (angle plane, then magnitude plane).
+enum WsPlane { TH = 0, VM, IVM, VRE, VIM, IRE, IIM, PIN, QIN, FP = 9, DXP = 11, WS_PLANES = 13 };
+
+template <int BLOCK, int KB>
+struct Ws {
+  static constexpr unsigned NBP = (unsigned)KB * BLOCK;
+  Buf b;
+  // plane a, bus slot k (k < 2 KB for the two-plane vectors F and DX)
+  __device__ __forceinline__ double ld(int a, int k) const {
+    return bld<double>(b, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
   }
-  if (f.k > 0) {
-    for (int i = f.c + (int)threadIdx.x; i < f.N; i += BLOCK) {
-      T a = xs[i];
-      const int pe = gld(f.L_ptr, i + 1);
-      for (int p = gld(f.L_ptr, i); p < pe; ++p) a -= gld(f.L_val, p) * xs[gld(f.L_col, p)];
-      tmp[i - f.c] = a;
-    }
-    __syncthreads();
-    for (int i = (int)threadIdx.x; i < f.k; i += BLOCK) {
-      T a0 = 0, a1 = 0;
-      unsigned o = i;
-      int l = 0;
-      for (; l + 1 < f.k; l += 2, o += 2 * f.k) {
-        a0 += gld(f.Sinv, o) * tmp[l];
-        a1 += gld(f.Sinv, o + f.k) * tmp[l + 1];
+  __device__ __forceinline__ void st(int a, int k, double v) const {
+    bst(b, v, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
+  }
+};
+
+// The Krylov basis of one scenario: vectors of MP = 2 NBP entries of T.
+template <typename T, int BLOCK, int KB>
+struct Basis {
+  static constexpr unsigned MP = 2u * KB * BLOCK;
+  Buf b;
+  __device__ __forceinline__ T ld(int i, int k) const {
+    return bld<T>(b, threadIdx.x * (unsigned)sizeof(T), ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+  }
+  __device__ __forceinline__ void st(int i, int k, T v) const {
+    bst(b, v, threadIdx.x * (unsigned)sizeof(T), ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+  }
+};
+
+// Rows by bus slot: the thread's bus slots k < KB are rows of slices
+// k NW + wave.  Slices are padded to widths that are multiples of 4 (with zero
+// entries), so each row is read in rounds of 4 independent entries with no
+// remainder loop.  body(k, val, col) accumulates one entry of slot k; after a
+// slot's row, done(k) runs and its results are pinned so that later slots do
+// not keep this slot's operands alive.
+template <int KB, int NW, typename V, typename Body, typename Done>
+__device__ __forceinline__ void sell_slots(const Sell<V>& a, Body&& body, Done&& done) {
+  const int wv = wave_id(), lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int o = cld(a.off, (unsigned)(k * NW + wv));
+    const int wd = cld(a.width, (unsigned)(k * NW + wv));
+    for (int p = 0; p < wd; p += 4) {
+      V v[4];
+      int c[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
+        v[u] = cld(a.val, q);
+        c[u] = cld(a.col, q);
       }
-      if (l < f.k) a0 += gld(f.Sinv, o) * tmp[l];
-      xs[f.c + i] = a0 + a1;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) body(k, v[u], c[u]);
     }
-  }
-  for (int j = (int)threadIdx.x; j < f.c; j += BLOCK) xs[j] *= gld(f.dinv, j);
-  __syncthreads();
-  for (int l = 0; l < f.nbl; ++l) {
-    const int s = gld(f.b_lev, l), e = gld(f.b_lev, l + 1);
-    for (int q = s + (int)threadIdx.x; q < e; q += BLOCK) {
-      const int j = gld(f.b_rows, q);
-      T a = xs[j];
-      const int pe = gld(f.T_ptr, j + 1);
-      for (int p = gld(f.T_ptr, j); p < pe; ++p) a -= gld(f.T_val, p) * xs[gld(f.T_col, p)];
-      xs[j] = a;
-    }
-    __syncthreads();
+    done(k);
   }
 }
 
-// Per-scenario views into the FP64 workspace (7 n + 2 mp doubles, mp = kd
-// BLOCK >= m the padded state length).
-struct Scen {
-  double* th;   // [n] angle
-  double* vm;   // [n] magnitude
-  double* ivm;  // [n] 1 / magnitude
-  double* vre;  // [n] V
-  double* vim;
-  double* ire;  // [n] I = Ybus V
-  double* iim;
-  double* F;    // [mp] mismatch, then the GMRES right-hand side (zero past m)
-  double* dx;   // [mp] Newton step
-};
+// out[k] -= or = sum over slot k's row of val * x[col], real values
+template <int KB, int NW, typename T>
+__device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (&acc)[KB]) {
+#pragma unroll
+  for (int k = 0; k < KB; ++k) acc[k] = 0;
+  sell_slots<KB, NW>(
+      a, [&](int k, T v, int c) { acc[k] += v * x[c]; }, [&](int k) { settle(acc[k]); });
+}
 
-__device__ inline Scen scen_at(double* ws, int n, unsigned mp) {
-  return Scen{ws, ws + n, ws + 2 * n, ws + 3 * n, ws + 4 * n, ws + 5 * n, ws + 6 * n, ws + 7 * n,
-              ws + 7 * n + mp};
+// out[OFF + k] = (A^-1 x)_i for the bus slots i = t + k BLOCK (zero past N), by
+// the explicit factor passes E1 (rows into `aux` / the core right-hand side
+// into `tmp`), E2 (dense core into aux past c), E3 (rows in matrix order, read
+// from aux).  x holds the right-hand side in matrix order; aux (N entries)
+// must not overlap it.  Two barriers; the caller places one before aux or tmp
+// is written again.
+template <typename T, int BLOCK, int KB, int OFF, int K>
+__device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K]) {
+  constexpr int NW = BLOCK / WAVE;
+  const int lane = lane_id(), wv = wave_id();
+#pragma unroll
+  for (int q = 0; q < KB; ++q) {
+    // (entry offset, width, first row) of this wave's q-th slice; width 0 past its list
+    const int4 t = cld(reinterpret_cast<const int4*>(f.e1_wave), (unsigned)(wv * KB + q));
+    if (t.y > 0) {
+      const int r = cld(f.e1_row, (unsigned)(t.z + lane));
+      T acc = 0;
+      for (int p = 0; p < t.y; p += 4) {  // widths are multiples of 4
+        T v[4];
+        int c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const unsigned qq = (unsigned)(t.x + (p + u) * WAVE + lane);
+          v[u] = cld(f.e1.val, qq);
+          c[u] = cld(f.e1.col, qq);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * x[c[u]];
+      }
+      if (r >= f.c) tmp[r - f.c] = acc;
+      else if (r >= 0) aux[r] = acc;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < f.k; i += BLOCK) {
+    T acc[4] = {0, 0, 0, 0};
+    int l = 0;
+    for (; l + 15 < f.k; l += 16) {
+      T v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) v[u] = cld(f.sinv, (unsigned)((l + u) * f.k + i));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u & 3] += v[u] * tmp[l + u];
+    }
+    for (; l < f.k; ++l) acc[0] += cld(f.sinv, (unsigned)(l * f.k + i)) * tmp[l];
+    aux[f.c + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  __syncthreads();
+  T acc[KB];
+  sell_slots_dot<KB, NW>(f.e3, aux, acc);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) out[OFF + k] = acc[k];
 }
 
 // z = M^-1 w for the left preconditioner of eq. (7), by the forward block
 // substitution of eqs. (8)-(9):
 //   z_Theta = (B' + eps I)^-1 diag(|V_Theta|)^-1 w_Theta
 //   z_Q     = (B'' + eps I)^-1 diag(|V_Q|)^-1 (w_Q - G z_Theta)
-template <typename T, int BLOCK, int K>
-__device__ void precond(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], T* xs, T* tmp) {
-  const unsigned nth = net.nth, m = net.m;
-  T* x1 = xs;
-  T* x2 = xs + nth;
+// LDS use: the B' right-hand side at [0, nth) with its passes at [nth, 2 nth);
+// z_Theta at [0, nth); the B'' right-hand side at [nth, nth + npq) with its
+// passes at [0, npq).  The caller guarantees that no thread still reads the
+// LDS vector area.
+template <typename T, int BLOCK, int KB>
+__device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB], const Smem<T>& s) {
+  constexpr int NW = BLOCK / WAVE;
+  const TxDev<T> net = load_desc(netp);
+  const unsigned nth = net.nth, npq = net.npq;
+  T* X = s.xs;
+  T* Y = s.xs + nth;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const unsigned r = row<BLOCK>(k);
-    if (k < kd && r < nth) x1[gld(net.bp.pinv, r)] = w[k] * (T)gld(sc.ivm, r);
+  for (int k = 0; k < KB; ++k) {
+    const unsigned i = row<BLOCK>(k);
+    const T v = w[k] * (T)ws.ld(IVM, k);
+    if (i < nth) X[i] = v;
   }
   __syncthreads();
-  spd_apply<T, BLOCK>(net.bp, x1, tmp);
-  if (net.npq > 0) {
-#pragma unroll 1
-    for (int k = 0; k < kd; ++k) {
-      const unsigned r = row<BLOCK>(k);
-      if (r >= nth && r < m) {
-        const unsigned q = r - nth;
-        T t = rget(w, k);
-        const int pe = gld(net.g_ptr, q + 1);
-        for (int p = gld(net.g_ptr, q); p < pe; ++p) t -= gld(net.g_val, p) * x1[gld(net.g_col, p)];
-        x2[gld(net.bpp.pinv, q)] = t * (T)gld(sc.ivm, q);
-      }
+  efac_apply<T, BLOCK, KB, 0>(net.bp, X, Y, s.tmp, w);
+  if (npq > 0) {
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if (i < nth) X[i] = w[k];
     }
     __syncthreads();
-    spd_apply<T, BLOCK>(net.bpp, x2, tmp);
-  }
+    const TxDev<T> nt = load_desc(netp);
+    T gz[KB];
+    sell_slots_dot<KB, NW>(nt.g, X, gz);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const unsigned r = row<BLOCK>(k);
-    if (k < kd) {
-      if (r < nth) w[k] = x1[gld(net.bp.pinv, r)];
-      else if (r < m) w[k] = x2[gld(net.bpp.pinv, r - nth)];
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      const T t = (w[KB + k] - gz[k]) * (T)ws.ld(IVM, k);
+      if (i < npq) Y[i] = t;
     }
+    __syncthreads();
+    efac_apply<T, BLOCK, KB, KB>(nt.bpp, Y, X, s.tmp, w);
   }
-  __syncthreads();
 }
 
 // w <- J w, the Jacobian of the mismatch at the current V (with I = Ybus V).
-template <typename T, int BLOCK, int K>
-__device__ void jvp(const TxDev<T>& net, const Scen& sc, int kd, T (&w)[K], T* xs) {
-  const int nth = net.nth, npq = net.npq;
-  const unsigned m = net.m;
+// Ends with a barrier.
+template <typename T, int BLOCK, int KB>
+__device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB], T* lds) {
+  using T2 = typename Vec2<T>::type;
+  const TxDev<T> net = load_desc(netp);
+  constexpr int NW = BLOCK / WAVE;
+  const unsigned nth = net.nth, npq = net.npq;
+  T2* dv = reinterpret_cast<T2*>(lds);
+  // dV_i = V_i (j p_theta + p_|V| / |V|)
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const unsigned r = row<BLOCK>(k);
-    if (k < kd && r < m) xs[r] = w[k];
+  for (int k = 0; k < KB; ++k) {
+    const unsigned i = row<BLOCK>(k);
+    const T a = w[KB + k] * (T)ws.ld(IVM, k);
+    const T vr = (T)ws.ld(VRE, k), vi = (T)ws.ld(VIM, k);
+    T2 d;
+    d.x = vr * a - vi * w[k];
+    d.y = vi * a + vr * w[k];
+    dv[i] = d;
   }
   __syncthreads();
-  // dV_b = V_b (j p_theta + p_|V| / |V|)
-  auto dv = [&](int bus, T& dr, T& di) {
-    const T pth = bus < nth ? xs[bus] : (T)0;
-    const T a = bus < npq ? xs[nth + bus] * (T)gld(sc.ivm, bus) : (T)0;
-    const T vr = (T)gld(sc.vre, bus), vi = (T)gld(sc.vim, bus);
-    dr = vr * a - vi * pth;
-    di = vi * a + vr * pth;
-  };
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const unsigned r = row<BLOCK>(k);
-    if (r < m) {
-      const int i = (int)r < nth ? (int)r : (int)r - nth;
-      T dIr = 0, dIi = 0;
-      const int pe = gld(net.y_ptr, i + 1);
-      for (int p = gld(net.y_ptr, i); p < pe; ++p) {
-        T dr, di;
-        dv(gld(net.y_col, p), dr, di);
-        const T yr = (T)gld(net.y_re, p), yi = (T)gld(net.y_im, p);
-        dIr += yr * dr - yi * di;
-        dIi += yr * di + yi * dr;
-      }
-      T dVr, dVi;
-      dv(i, dVr, dVi);
-      const T Ir = (T)gld(sc.ire, i), Ii = (T)gld(sc.iim, i);
-      const T vr = (T)gld(sc.vre, i), vi = (T)gld(sc.vim, i);
-      // dS = dV conj(I) + V conj(dI): real part on Theta rows, imaginary on Q rows
-      rset(w, k, (int)r < nth ? dVr * Ir + dVi * Ii + vr * dIr + vi * dIi
-                              : dVi * Ir - dVr * Ii + vi * dIr - vr * dIi);
-    }
-  }
+  T dIr = 0, dIi = 0;
+  sell_slots<KB, NW>(
+      net.yT,
+      [&](int, T2 y, int c) {
+        const T2 d = dv[c];
+        dIr += y.x * d.x - y.y * d.y;
+        dIi += y.x * d.y + y.y * d.x;
+      },
+      [&](int k) {
+        const unsigned i = row<BLOCK>(k);
+        const T2 d = dv[i];
+        const T Ir = (T)ws.ld(IRE, k), Ii = (T)ws.ld(IIM, k);
+        const T vr = (T)ws.ld(VRE, k), vi = (T)ws.ld(VIM, k);
+        // dS = dV conj(I) + V conj(dI): real part on Theta, imaginary part on Q
+        w[k] = i < nth ? d.x * Ir + d.y * Ii + vr * dIr + vi * dIi : (T)0;
+        w[KB + k] = i < npq ? d.y * Ir - d.x * Ii + vi * dIr - vr * dIi : (T)0;
+        settle(w[k]);
+        settle(w[KB + k]);
+        dIr = dIi = 0;
+      });
   __syncthreads();
 }
 
-// h[i] = <basis_i, w> for i < nv and, if `ss` is not null, h[nv] = sum of *ss
-// over the workgroup.  Results in LDS h; ends with a barrier.
-template <typename T, int BLOCK, int K>
-__device__ void multi_dot(const T* basis, unsigned stride, int nv, int kd, const T (&w)[K], const T* ss,
-                          T* red, T* h) {
+// Writes part[i NW + wave] = the wave's share of <basis_i, w> for i < nv and
+// part[nv NW + wave] = the wave's share of ss; ends with a barrier.
+template <typename T, int BLOCK, int KB>
+__device__ void multi_dot(const Basis<T, BLOCK, KB>& basis, int nv, const T (&w)[2 * KB], T ss, T* part) {
   constexpr int NW = BLOCK / WAVE;
-  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  const int lane = lane_id(), wid = wave_id();
   int i = 0;
-  for (; i + 1 < nv; i += 2) {
-    const T* v0 = basis + (unsigned)i * stride;
-    const T* v1 = v0 + stride;
+  for (; i + 1 < nv; i += 2) {  // two vectors per round: twice the loads in flight
     T a0 = 0, a1 = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      if (k < kd) {
-        a0 += gld(v0, row<BLOCK>(k)) * w[k];
-        a1 += gld(v1, row<BLOCK>(k)) * w[k];
-      }
+    for (int k = 0; k < 2 * KB; ++k) {
+      a0 += basis.ld(i, k) * w[k];
+      a1 += basis.ld(i + 1, k) * w[k];
     }
-    a0 = wave_sum(a0);
-    a1 = wave_sum(a1);
+    a0 = wave_total(a0);
+    a1 = wave_total(a1);
     if (lane == 0) {
-      red[i * NW + wid] = a0;
-      red[(i + 1) * NW + wid] = a1;
+      part[i * NW + wid] = a0;
+      part[(i + 1) * NW + wid] = a1;
     }
   }
   if (i < nv) {
-    const T* v0 = basis + (unsigned)i * stride;
     T a0 = 0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kd) a0 += gld(v0, row<BLOCK>(k)) * w[k];
-    a0 = wave_sum(a0);
-    if (lane == 0) red[i * NW + wid] = a0;
+    for (int k = 0; k < 2 * KB; ++k) a0 += basis.ld(i, k) * w[k];
+    a0 = wave_total(a0);
+    if (lane == 0) part[i * NW + wid] = a0;
   }
-  const int nout = ss ? nv + 1 : nv;
-  if (ss) {
-    const T a = wave_sum(*ss);
-    if (lane == 0) red[nv * NW + wid] = a;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < nout; q += BLOCK) {
-    T s = 0;
-#pragma unroll
-    for (int u = 0; u < NW; ++u) s += red[q * NW + u];
-    h[q] = s;
-  }
+  ss = wave_total(ss);
+  if (lane == 0) part[nv * NW + wid] = ss;
   __syncthreads();
 }
 
-// w -= sum_i h[i] basis_i
-template <typename T, int BLOCK, int K>
-__device__ void subtract_proj(const T* basis, unsigned stride, int nv, int kd, T (&w)[K], const T* h) {
+template <typename T, int NW>
+__device__ __forceinline__ T part_sum(const T* part, int i) {
+  T s = 0;
+#pragma unroll
+  for (int u = 0; u < NW; ++u) s += part[i * NW + u];
+  return s;
+}
+
+// w -= sum_i h_i basis_i with h_i from the partials; returns sum_i h_i^2.
+template <typename T, int BLOCK, int KB>
+__device__ T subtract_proj(const Basis<T, BLOCK, KB>& basis, int nv, T (&w)[2 * KB], const T* part) {
+  constexpr int NW = BLOCK / WAVE;
+  T hh = 0;
   int i = 0;
   for (; i + 1 < nv; i += 2) {
-    const T h0 = h[i], h1 = h[i + 1];
-    const T* v0 = basis + (unsigned)i * stride;
-    const T* v1 = v0 + stride;
+    const T h0 = part_sum<T, NW>(part, i), h1 = part_sum<T, NW>(part, i + 1);
+    hh += h0 * h0 + h1 * h1;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kd) w[k] -= h0 * gld(v0, row<BLOCK>(k)) + h1 * gld(v1, row<BLOCK>(k));
+    for (int k = 0; k < 2 * KB; ++k) w[k] -= h0 * basis.ld(i, k) + h1 * basis.ld(i + 1, k);
   }
   if (i < nv) {
-    const T h0 = h[i];
-    const T* v0 = basis + (unsigned)i * stride;
+    const T h0 = part_sum<T, NW>(part, i);
+    hh += h0 * h0;
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kd) w[k] -= h0 * gld(v0, row<BLOCK>(k));
+    for (int k = 0; k < 2 * KB; ++k) w[k] -= h0 * basis.ld(i, k);
   }
+  return hh;
 }
 
 // Mismatch at the current (theta, |V|): writes V, 1/|V|, I and F to the
-// workspace and returns max |F| (NaN if any entry is NaN).
-template <typename T, int BLOCK, int K>
-__device__ double mismatch(const TxDev<T>& net, const Scen& sc, int kd, const double* P, const double* Q,
-                           double* vs, double* red) {
-  const int n = net.n, nth = net.nth, m = net.m;
-  const int* ext = net.int2ext;
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    double s, c;
-    sincos(gld(sc.th, i), &s, &c);
-    const double vm = gld(sc.vm, i);
-    const double vr = vm * c, vi = vm * s;
-    gst(sc.vre, i, vr);
-    gst(sc.vim, i, vi);
-    gst(sc.ivm, i, 1.0 / vm);
-    vs[2 * i] = vr;
-    vs[2 * i + 1] = vi;
+// workspace and returns max |F| (NaN if any entry is NaN).  Ends with a barrier.
+template <typename T, int BLOCK, int KB>
+__device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double2* vs, double* part) {
+  constexpr int NW = BLOCK / WAVE;
+  const TxDev<T> net = load_desc(netp);
+  const unsigned nth = net.nth, npq = net.npq;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    slot_fence();
+    const unsigned i = row<BLOCK>(k);
+    double sn, cs;
+    sincos(ws.ld(TH, k), &sn, &cs);
+    const double vm = ws.ld(VM, k);
+    double2 v;
+    v.x = vm * cs;
+    v.y = vm * sn;
+    ws.st(VRE, k, v.x);
+    ws.st(VIM, k, v.y);
+    ws.st(IVM, k, 1.0 / vm);
+    vs[i] = v;
   }
   __syncthreads();
-  double fmax = 0.0;
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (r >= m) {
-      gst(sc.F, r, 0.0);  // padding rows of the right-hand side stay zero
-    } else {
-      const int i = r < nth ? r : r - nth;
-      double Ir = 0.0, Ii = 0.0;
-      const int pe = gld(net.y_ptr, i + 1);
-      for (int p = gld(net.y_ptr, i); p < pe; ++p) {
-        const int c = gld(net.y_col, p);
-        const double yr = gld(net.y_re, p), yi = gld(net.y_im, p);
-        const double vr = vs[2 * c], vi = vs[2 * c + 1];
-        Ir += yr * vr - yi * vi;
-        Ii += yr * vi + yi * vr;
-      }
-      const double vr = vs[2 * i], vi = vs[2 * i + 1];
-      double f;
-      if (r < nth) {
-        gst(sc.ire, i, Ir);
-        gst(sc.iim, i, Ii);
-        f = vr * Ir + vi * Ii - gld(P, gld(ext, i));
-      } else {
-        f = vi * Ir - vr * Ii - gld(Q, gld(ext, i));
-      }
-      gst(sc.F, r, f);
-      fmax = nanmax(fmax, fabs(f));
-    }
-  }
-  return block_nanmax<BLOCK>(fmax, red);
+  double Ir = 0.0, Ii = 0.0, fmax = 0.0;
+  sell_slots<KB, NW>(
+      net.y64,
+      [&](int, double2 y, int c) {
+        const double2 v = vs[c];
+        Ir += y.x * v.x - y.y * v.y;
+        Ii += y.x * v.y + y.y * v.x;
+      },
+      [&](int k) {
+        const unsigned i = row<BLOCK>(k);
+        const double2 v = vs[i];
+        ws.st(IRE, k, Ir);
+        ws.st(IIM, k, Ii);
+        const double ft = i < nth ? v.x * Ir + v.y * Ii - ws.ld(PIN, k) : 0.0;
+        const double fv = i < npq ? v.y * Ir - v.x * Ii - ws.ld(QIN, k) : 0.0;
+        ws.st(FP, k, ft);
+        ws.st(FP, KB + k, fv);
+        fmax = nanmax(fmax, nanmax(fabs(ft), fabs(fv)));
+        settle(fmax);
+        Ir = Ii = 0.0;
+      });
+  return block_nanmax<BLOCK>(fmax, part);
 }
 
 // Algorithmic HBM bytes of one scenario (the byte model reported with the
@@ -504,39 +682,50 @@ struct ByteModel {
 // ||M^-1 (b - A x)|| reaches rtol ||M^-1 b||, after max_restarts cycles, or at
 // a breakdown.  Returns the number of Arnoldi steps; *converged tells whether
 // the tolerance was met.
-template <typename T, int BLOCK, int K, typename ApplyA, typename ApplyM>
-__device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs, double* x, T* basis,
-                           unsigned mp, int kd, int R, int max_restarts, T rtol, const Smem<T>& s,
+//
+// Orthogonalisation runs on w = A v_j - v_j (see below).  One reduction gives
+// <v_i, w> and ||w||^2 together, and
+// ||w'||^2 = ||w||^2 - sum h_i^2 after the projection; a second pass runs when
+// that cancels more than half of ||w||^2.  Every thread applies the Givens
+// rotations to the new Hessenberg column itself (same data, same operations),
+// so no barrier is needed after them; thread 0 alone stores H, the rotations
+// and the rotated right-hand side for later steps.
+template <typename T, int BLOCK, int KB, typename ApplyA, typename ApplyM>
+__device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, KB>& ws, int bpl, int xpl,
+                           const Basis<T, BLOCK, KB>& basis, int R, int max_restarts, T rtol, const Smem<T>& s,
                            bool* converged, const ByteModel& bm, double* work) {
+  constexpr int NW = BLOCK / WAVE;
+  constexpr int K = 2 * KB;
+  const unsigned pstride = (unsigned)(R + 2) * NW;
+  int par = 0;
+  auto next_part = [&]() {
+    T* p = s.red + par * pstride;
+    par ^= 1;
+    return p;
+  };
   T w[K];
   T beta0 = 0;
   int total = 0;
   bool done = false;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    w[k] = 0;
-    if (k < kd) gst(x, row<BLOCK>(k), 0.0);
-  }
+  for (int k = 0; k < K; ++k) ws.st(xpl, k, 0.0);
   for (int cycle = 0; cycle < max_restarts && !done; ++cycle) {
     *work += (cycle > 0 ? bm.jvp() : 0.0) + bm.pre() + bm.m8 + bm.wm;
     if (cycle == 0) {
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)gld(rhs, row<BLOCK>(k));
+      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k);
     } else {
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)gld(x, row<BLOCK>(k));
+      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(xpl, k);
       apply_a(w);
 #pragma unroll
-      for (int k = 0; k < K; ++k)
-        if (k < kd) w[k] = (T)gld(rhs, row<BLOCK>(k)) - w[k];
+      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k) - w[k];
     }
     apply_m(w);
     T ss = 0;
 #pragma unroll
     for (int k = 0; k < K; ++k) ss += w[k] * w[k];
-    const T beta = sqrt(block_sum<T, BLOCK>(ss, s.red));
+    const T beta = sqrt(block_sum<T, BLOCK>(ss, next_part()));
     if (cycle == 0) beta0 = beta;
     if (!(beta > rtol * beta0) || beta == (T)0) {
       done = !(beta > rtol * beta0);
@@ -546,65 +735,72 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       w[k] *= ib;
-      if (k < kd) gst(basis, row<BLOCK>(k), w[k]);
+      basis.st(0, k, w[k]);
     }
-    if (threadIdx.x == 0) s.g[0] = beta;
+    if (threadIdx.x == 0) s.gres[0] = beta;
     int steps = 0;
     T res = beta;
     for (int j = 0; j < R; ++j) {
       apply_a(w);
       apply_m(w);
+      // Arnoldi on A - I: the same Krylov space (H = H' + I), and with a good
+      // preconditioner A v_j is close to v_j, so the shifted vector loses far
+      // less to the projection than A v_j itself would.
+#pragma unroll
+      for (int k = 0; k < K; ++k) w[k] -= basis.ld(j, k);
       T ss0 = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) ss0 += w[k] * w[k];
-      multi_dot<T, BLOCK, K>(basis, mp, j + 1, kd, w, &ss0, s.red, s.h1);
-      subtract_proj<T, BLOCK, K>(basis, mp, j + 1, kd, w, s.h1);
-      T s1 = 0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) s1 += w[k] * w[k];
-      T nrm2 = block_sum<T, BLOCK>(s1, s.red);
-      // second pass when the first removed more than 1 - 1/sqrt(2) of the norm
-      const bool again = nrm2 < (T)0.5 * s.h1[j + 1];
+      T* p1 = next_part();
+      multi_dot<T, BLOCK, KB>(basis, j + 1, w, ss0, p1);
+      const T hh1 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
+      const T wn2 = part_sum<T, NW>(p1, j + 1);
+      T nrm2 = wn2 - hh1;
+      // second pass when the first removed more than half of the squared norm
+      const bool again = nrm2 < (T)0.5 * wn2;
+      T* p2 = p1;
       if (again) {
-        multi_dot<T, BLOCK, K>(basis, mp, j + 1, kd, w, nullptr, s.red, s.h2);
-        subtract_proj<T, BLOCK, K>(basis, mp, j + 1, kd, w, s.h2);
-        T s2 = 0;
+        T s1 = 0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) s2 += w[k] * w[k];
-        nrm2 = block_sum<T, BLOCK>(s2, s.red);
+        for (int k = 0; k < K; ++k) s1 += w[k] * w[k];
+        p2 = next_part();
+        multi_dot<T, BLOCK, KB>(basis, j + 1, w, s1, p2);
+        const T hh2 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p2);
+        nrm2 = part_sum<T, NW>(p2, j + 1) - hh2;
       }
       *work += bm.jvp() + bm.pre() + (again ? 2 : 1) * bm.orth_pass(j);
-      const T hn = sqrt(nrm2);
+      const T hn = sqrt(nrm2 > (T)0 ? nrm2 : (T)0);
+      // Hessenberg column j: h_i (+ second-pass h_i), rotated by the previous Givens rotations
+      T* Hj = s.H + hcol(j);
+      T cur = part_sum<T, NW>(p1, 0) + (again ? part_sum<T, NW>(p2, 0) : (T)0) + (j == 0 ? (T)1 : (T)0);
+      for (int i = 0; i < j; ++i) {
+        const T nxt = part_sum<T, NW>(p1, i + 1) + (again ? part_sum<T, NW>(p2, i + 1) : (T)0) +
+                      (i + 1 == j ? (T)1 : (T)0);
+        const T c = s.cs[i], sn = s.sn[i];
+        const T a = c * cur + sn * nxt;
+        cur = -sn * cur + c * nxt;
+        if (threadIdx.x == 0) Hj[i] = a;
+      }
+      const T d = sqrt(cur * cur + hn * hn);
+      const T c = d == (T)0 ? (T)1 : cur / d;
+      const T sn = d == (T)0 ? (T)0 : hn / d;
+      const T gj = s.gres[j];
+      const T gnext = -sn * gj;
       if (threadIdx.x == 0) {
-        T* Hj = s.H + hcol(j);
-        for (int i = 0; i <= j; ++i) Hj[i] = again ? s.h1[i] + s.h2[i] : s.h1[i];
-        Hj[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-          const T t = s.cs[i] * Hj[i] + s.sn[i] * Hj[i + 1];
-          Hj[i + 1] = -s.sn[i] * Hj[i] + s.cs[i] * Hj[i + 1];
-          Hj[i] = t;
-        }
-        const T d = sqrt(Hj[j] * Hj[j] + Hj[j + 1] * Hj[j + 1]);
-        const T c = d == (T)0 ? (T)1 : Hj[j] / d;
-        const T sn = d == (T)0 ? (T)0 : Hj[j + 1] / d;
+        Hj[j] = d;
         s.cs[j] = c;
         s.sn[j] = sn;
-        Hj[j] = d;
-        Hj[j + 1] = 0;
-        s.g[j + 1] = -sn * s.g[j];
-        s.g[j] = c * s.g[j];
-        s.misc[0] = fabs(s.g[j + 1]);
+        s.gres[j + 1] = gnext;
+        s.gfin[j] = c * gj;
       }
-      __syncthreads();
-      res = s.misc[0];
+      res = fabs(gnext);
       steps = j + 1;
       if (!(res > rtol * beta0) || j == R - 1 || !(hn > (T)0)) break;
       const T ih = (T)1 / hn;
-      T* vnext = basis + (unsigned)(j + 1) * mp;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         w[k] *= ih;
-        if (k < kd) gst(vnext, row<BLOCK>(k), w[k]);
+        basis.st(j + 1, k, w[k]);
       }
     }
     total += steps;
@@ -612,68 +808,86 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const double* rhs
     // y = H^-1 g (upper triangular after the rotations)
     if (threadIdx.x == 0) {
       for (int i = steps - 1; i >= 0; --i) {
-        T a = s.g[i];
+        T a = s.gfin[i];
         for (int l = i + 1; l < steps; ++l) a -= s.H[hcol(l) + i] * s.yv[l];
         const T d = s.H[hcol(i) + i];
         s.yv[i] = d != (T)0 ? a / d : (T)0;
       }
     }
     __syncthreads();
-#pragma unroll 1
-    for (int k = 0; k < kd; ++k) {
-      const unsigned r = row<BLOCK>(k);
-      double acc = gld(x, r);
-      for (int i = 0; i < steps; ++i) acc += (double)s.yv[i] * (double)gld(basis, (unsigned)i * mp + r);
-      gst(x, r, acc);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double acc = ws.ld(xpl, k);
+      for (int i = 0; i < steps; ++i) acc += (double)s.yv[i] * (double)basis.ld(i, k);
+      ws.st(xpl, k, acc);
     }
     done = !(res > rtol * beta0);
-    __syncthreads();
   }
   *converged = done;
   return total;
 }
 
-template <typename T, int BLOCK, int K>
-// Four waves per SIMD: with about 39 KB of LDS per scenario, four workgroups
+template <typename T, int BLOCK, int KB>
+// Four waves per SIMD: with about 40 KB of LDS per scenario, four workgroups
 // (four scenarios) share a CU; registers are capped to match.
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void nr_kernel(const TxDev<T>* __restrict__ netp, NRLaunch a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void nr_kernel(
+    const TxDev<T>* __restrict__ netp, NRLaunch a) {
   constexpr int NW = BLOCK / WAVE;
+  constexpr int K = 2 * KB;
   extern __shared__ __align__(16) unsigned char smem[];
-  const TxDev<T>& net = *netp;
   const int b = blockIdx.x;
-  const int n = net.n, nth = net.nth, npq = net.npq, m = net.m;
-  const int R = a.restart;
-  const int kmax = net.bp.k > net.bpp.k ? net.bp.k : net.bpp.k;
-  const NrLayout L = nr_layout(n, m, kmax, R, NW, (int)sizeof(T));
-  const Smem<T> s = carve<T>(smem, L);
-  const int kd = ((n > m ? n : m) + BLOCK - 1) / BLOCK;
-  const unsigned mp = (unsigned)kd * BLOCK;
-
-  const Scen sc = scen_at(a.ws_d + (int64_t)b * a.ws_d_stride, n, mp);
-  T* basis = reinterpret_cast<T*>(a.ws_basis) + (int64_t)b * a.ws_b_stride;
-  const double* P = a.p_inj + (int64_t)b * a.ld;
-  const double* Q = a.q_inj + (int64_t)b * a.ld;
-  const double* VS = a.vm_set + (int64_t)b * a.ld;
-  const int* ext = net.int2ext;
-
-  // flat start: theta = 0, |V| = set-point at PV and slack, 1 at PQ buses
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    gst(sc.th, i, 0.0);
-    gst(sc.vm, i, i < npq ? 1.0 : gld(VS, gld(ext, i)));
+  int n, npq, kmax;
+  {
+    const TxDev<T> net = load_desc(netp);
+    n = net.n;
+    npq = net.npq;
+    kmax = net.bp.k > net.bpp.k ? net.bp.k : net.bpp.k;
   }
-  __syncthreads();
+  const int R = a.restart;
+  const NrLayout L = nr_layout(KB * BLOCK, n - 1, npq, kmax, R, NW, (int)sizeof(T));
+  const Smem<T> s = carve<T>(smem, L);
 
-  auto apply_j = [&](T (&w)[K]) { jvp<T, BLOCK, K>(net, sc, kd, w, s.xs); };
-  auto apply_m = [&](T (&w)[K]) { precond<T, BLOCK, K>(net, sc, kd, w, s.xs, s.tmp); };
+  const Ws<BLOCK, KB> ws{make_buf(a.ws_d + (int64_t)b * a.ws_d_stride)};
+  const Basis<T, BLOCK, KB> basis{make_buf(reinterpret_cast<T*>(a.ws_basis) + (int64_t)b * a.ws_b_stride)};
+  const Buf P = make_buf(a.p_inj + (int64_t)b * a.ld);
+  const Buf Q = make_buf(a.q_inj + (int64_t)b * a.ld);
+  const Buf VS = make_buf(a.vm_set + (int64_t)b * a.ld);
+
+  // flat start: theta = 0, |V| = set-point at PV and slack, 1 at PQ buses;
+  // scheduled injections in internal order (padding buses: |V| = 1, no injection)
+  {
+    const TxDev<T> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      double p = 0.0, q = 0.0, vs = 1.0;
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 8u;
+        p = bld<double>(P, e, 0);
+        q = bld<double>(Q, e, 0);
+        if ((int)i >= npq) vs = bld<double>(VS, e, 0);
+      }
+      ws.st(TH, k, 0.0);
+      ws.st(VM, k, vs);
+      ws.st(PIN, k, p);
+      ws.st(QIN, k, q);
+    }
+  }
+
+  auto apply_j = [&](T (&w)[K]) { jvp<T, BLOCK, KB>(netp, ws, w, s.xs); };
+  auto apply_m = [&](T (&w)[K]) { precond<T, BLOCK, KB>(netp, ws, w, s); };
 
   int newton = 0, gtotal = 0;
   bool conv = false;
   double fnorm = 0.0;
-  const ByteModel bm{(double)sizeof(T) * m, 8.0 * m, 8.0 * n};
   double work = 0.0;
+  int par = 0;
   for (;;) {
+    fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW);
+    const TxDev<T> net = load_desc(netp);
+    const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n};
     work += bm.mismatch();
-    fnorm = mismatch<T, BLOCK, K>(net, sc, kd, P, Q, s.vs, s.redd);
+    par ^= 1;
     if (!(fnorm <= a.diverge)) break;
     if (fnorm <= a.tol) {
       conv = true;
@@ -682,30 +896,32 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     if (newton >= a.max_newton) break;
     // right-hand side -F in place (own rows)
 #pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (k < kd) gst(sc.F, row<BLOCK>(k), -gld(sc.F, row<BLOCK>(k)));
+    for (int k = 0; k < K; ++k) ws.st(FP, k, -ws.ld(FP, k));
     bool lin_ok;
-    gtotal += gmres_solve<T, BLOCK, K>(apply_j, apply_m, sc.F, sc.dx, basis, mp, kd, R, a.max_restarts,
-                                       (T)a.rtol, s, &lin_ok, bm, &work);
-    // Newton update (eq. (3)), FP64, own rows
+    gtotal += gmres_solve<T, BLOCK, KB>(apply_j, apply_m, ws, FP, DXP, basis, R, a.max_restarts, (T)a.rtol, s,
+                                        &lin_ok, bm, &work);
+    // Newton update (eq. (3)), FP64, own buses
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int r = (int)row<BLOCK>(k);
-      if (k < kd) {
-        if (r < nth) gst(sc.th, r, gld(sc.th, r) + gld(sc.dx, r));
-        else if (r < m) gst(sc.vm, r - nth, gld(sc.vm, r - nth) + gld(sc.dx, r));
-      }
+    for (int k = 0; k < KB; ++k) {
+      ws.st(TH, k, ws.ld(TH, k) + ws.ld(DXP, k));
+      ws.st(VM, k, ws.ld(VM, k) + ws.ld(DXP, KB + k));
     }
     work += bm.update();
-    __syncthreads();
     ++newton;
   }
 
-  double* vout = a.v_out + 2 * (int64_t)b * a.ld;
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    const int e = gld(ext, i);
-    gst(vout, 2 * e, gld(sc.vre, i));
-    gst(vout, 2 * e + 1, gld(sc.vim, i));
+  const Buf vout = make_buf(a.v_out + 2 * (int64_t)b * a.ld);
+  {
+    const TxDev<T> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 16u;
+        bst(vout, ws.ld(VRE, k), e, 0);
+        bst(vout, ws.ld(VIM, k), e, 8);
+      }
+    }
   }
   if (threadIdx.x == 0) {
     a.newton_iters[b] = newton;
@@ -719,171 +935,204 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // ---------------------------------------------------------------------------
 // Adjoint.  For w = [w_P on Theta ; w_Q on Q] and c = w_P + j w_Q (zero where
 // undefined), w^T dF = Re sum_k g_k dV_k with g = conj(c I) + Ybus^T (c conj V),
-// so (J^T w) = [-Im(g V) on Theta ; Re(g V) / |V| on Q].
-template <int BLOCK, int K>
-__device__ void vjp(const TxDev<double>& net, const Scen& sc, int kd, double (&w)[K], double* xs) {
-  const int nth = net.nth, npq = net.npq, m = net.m;
+// so (J^T w) = [-Im(g V) on Theta ; Re(g V) / |V| on Q].  Ends with a barrier.
+template <int BLOCK, int KB>
+__device__ void vjp(const TxDev<double>* netp, const Ws<BLOCK, KB>& ws, double (&w)[2 * KB], double* lds) {
+  constexpr int NW = BLOCK / WAVE;
+  const TxDev<double> net = load_desc(netp);
+  const unsigned nth = net.nth, npq = net.npq;
+  double2* u = reinterpret_cast<double2*>(lds);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (k < kd && r < m) xs[r] = w[k];
+  for (int k = 0; k < KB; ++k) {
+    const unsigned i = row<BLOCK>(k);
+    const double cr = w[k], ci = w[KB + k];
+    const double vr = ws.ld(VRE, k), vi = ws.ld(VIM, k);
+    double2 t;  // c conj(V)
+    t.x = cr * vr + ci * vi;
+    t.y = ci * vr - cr * vi;
+    u[i] = t;
   }
   __syncthreads();
-  auto cc = [&](int bus, double& cr, double& ci) {
-    cr = bus < nth ? xs[bus] : 0.0;
-    ci = bus < npq ? xs[nth + bus] : 0.0;
-  };
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (r < m) {
-      const int i = r < nth ? r : r - nth;
-      double gr = 0.0, gi = 0.0;  // (Y^T (c conj V))_i
-      for (int p = net.yt_ptr[i]; p < net.yt_ptr[i + 1]; ++p) {
-        const int j = net.yt_col[p];
-        double cr, ci;
-        cc(j, cr, ci);
-        const double vr = sc.vre[j], vi = sc.vim[j];
-        const double ur = cr * vr + ci * vi, ui = ci * vr - cr * vi;  // c conj(V)
-        const double yr = net.yt_re[p], yi = net.yt_im[p];
-        gr += yr * ur - yi * ui;
-        gi += yr * ui + yi * ur;
-      }
-      double cr, ci;
-      cc(i, cr, ci);
-      const double Ir = sc.ire[i], Ii = sc.iim[i];
-      gr += cr * Ir - ci * Ii;  // conj(c I)
-      gi -= cr * Ii + ci * Ir;
-      const double vr = sc.vre[i], vi = sc.vim[i];
-      const double pr = gr * vr - gi * vi, pi = gr * vi + gi * vr;  // g V
-      rset(w, k, r < nth ? -pi : pr * sc.ivm[i]);
-    }
-  }
+  double gr = 0.0, gi = 0.0;  // (Y^T (c conj V))_i
+  sell_slots<KB, NW>(
+      net.yt,
+      [&](int, double2 y, int c) {
+        const double2 t = u[c];
+        gr += y.x * t.x - y.y * t.y;
+        gi += y.x * t.y + y.y * t.x;
+      },
+      [&](int k) {
+        const unsigned i = row<BLOCK>(k);
+        const double cr = w[k], ci = w[KB + k];
+        const double Ir = ws.ld(IRE, k), Ii = ws.ld(IIM, k);
+        const double hr = gr + cr * Ir - ci * Ii;  // + conj(c I)
+        const double hi = gi - (cr * Ii + ci * Ir);
+        const double vr = ws.ld(VRE, k), vi = ws.ld(VIM, k);
+        const double pr = hr * vr - hi * vi, pi = hr * vi + hi * vr;  // g V
+        w[k] = i < nth ? -pi : 0.0;
+        w[KB + k] = i < npq ? pr * ws.ld(IVM, k) : 0.0;
+        settle(w[k]);
+        settle(w[KB + k]);
+        gr = gi = 0.0;
+      });
   __syncthreads();
 }
 
 // z = M^-T w: z_Q = diag(|V_Q|)^-1 (B'' + eps I)^-1 w_Q,
 //             z_Theta = diag(|V_Theta|)^-1 (B' + eps I)^-1 (w_Theta - G^T z_Q).
-template <int BLOCK, int K>
-__device__ void precond_t(const TxDev<double>& net, const Scen& sc, int kd, double (&w)[K], double* xs,
-                          double* tmp) {
-  const int nth = net.nth, m = net.m;
-  double* x1 = xs;
-  double* x2 = xs + nth;
-  if (net.npq > 0) {
+// LDS use as in precond, with the roles of the two solves swapped.
+template <int BLOCK, int KB>
+__device__ void precond_t(const TxDev<double>* netp, const Ws<BLOCK, KB>& ws, double (&w)[2 * KB],
+                          const Smem<double>& s) {
+  constexpr int NW = BLOCK / WAVE;
+  const TxDev<double> net = load_desc(netp);
+  const unsigned nth = net.nth, npq = net.npq;
+  double* X = s.xs;
+  double* Y = s.xs + nth;
+  if (npq > 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int r = (int)row<BLOCK>(k);
-      if (k < kd && r >= nth && r < m) x2[net.bpp.pinv[r - nth]] = w[k];
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if (i < npq) Y[i] = w[KB + k];
     }
     __syncthreads();
-    spd_apply<double, BLOCK>(net.bpp, x2, tmp);
+    efac_apply<double, BLOCK, KB, KB>(net.bpp, Y, X, s.tmp, w);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int r = (int)row<BLOCK>(k);
-      if (k < kd && r >= nth && r < m) x2[net.bpp.pinv[r - nth]] *= sc.ivm[r - nth];
+    for (int k = 0; k < KB; ++k) w[KB + k] *= ws.ld(IVM, k);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if (i < npq) Y[i] = w[KB + k];
     }
     __syncthreads();
-  }
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (r < nth) {
-      double t = rget(w, k);
-      for (int p = net.gt_ptr[r]; p < net.gt_ptr[r + 1]; ++p) t -= net.gt_val[p] * x2[net.gt_col[p]];
-      x1[net.bp.pinv[r]] = t;
+    const TxDev<double> nt = load_desc(netp);
+    double gz[KB];
+    sell_slots_dot<KB, NW>(nt.gt, Y, gz);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if (i < nth) X[i] = w[k] - gz[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if (i < nth) X[i] = w[k];
     }
   }
   __syncthreads();
-  spd_apply<double, BLOCK>(net.bp, x1, tmp);
+  const TxDev<double> nb = load_desc(netp);
+  efac_apply<double, BLOCK, KB, 0>(nb.bp, X, Y, s.tmp, w);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (k < kd) {
-      if (r < nth) w[k] = x1[net.bp.pinv[r]] * sc.ivm[r];
-      else if (r < m) w[k] = x2[net.bpp.pinv[r - nth]];
-    }
-  }
-  __syncthreads();
+  for (int k = 0; k < KB; ++k) w[k] *= ws.ld(IVM, k);
 }
 
-template <int BLOCK, int K>
-__global__ __launch_bounds__(BLOCK) void adjoint_kernel(const TxDev<double>* __restrict__ netp, AdjLaunch a) {
+template <int BLOCK, int KB>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void adjoint_kernel(
+    const TxDev<double>* __restrict__ netp, AdjLaunch a) {
   constexpr int NW = BLOCK / WAVE;
+  constexpr int K = 2 * KB;
   extern __shared__ __align__(16) unsigned char smem[];
-  const TxDev<double>& net = *netp;
   const int b = blockIdx.x;
-  const int n = net.n, nth = net.nth, npq = net.npq, m = net.m;
+  int n, nth, npq, kmax;
+  {
+    const TxDev<double> net = load_desc(netp);
+    n = net.n;
+    nth = net.nth;
+    npq = net.npq;
+    kmax = net.bp.k > net.bpp.k ? net.bp.k : net.bpp.k;
+  }
   const int R = a.restart;
-  const int kmax = net.bp.k > net.bpp.k ? net.bp.k : net.bpp.k;
-  const NrLayout L = nr_layout(n, m, kmax, R, NW, 8);
+  const NrLayout L = nr_layout(KB * BLOCK, nth, npq, kmax, R, NW, 8);
   const Smem<double> s = carve<double>(smem, L);
-  const int kd = ((n > m ? n : m) + BLOCK - 1) / BLOCK;
-  const unsigned mp = (unsigned)kd * BLOCK;
-  const Scen sc = scen_at(a.ws_d + (int64_t)b * a.ws_d_stride, n, mp);
-  double* basis = a.ws_basis + (int64_t)b * a.ws_b_stride;
-  const int* ext = net.int2ext;
-  const double* V = a.v + 2 * (int64_t)b * a.ld;
-  const double* tg = a.dl_dv + 2 * (int64_t)b * a.ld;
+  const Ws<BLOCK, KB> ws{make_buf(a.ws_d + (int64_t)b * a.ws_d_stride)};
+  const Basis<double, BLOCK, KB> basis{make_buf(a.ws_basis + (int64_t)b * a.ws_b_stride)};
+  const Buf V = make_buf(a.v + 2 * (int64_t)b * a.ld);
+  const Buf tg = make_buf(a.dl_dv + 2 * (int64_t)b * a.ld);
 
-  // V, |V|, 1/|V| and I = Ybus V at the given voltages
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    const double vr = V[2 * ext[i]], vi = V[2 * ext[i] + 1];
-    const double vm = sqrt(vr * vr + vi * vi);
-    sc.vre[i] = vr;
-    sc.vim[i] = vi;
-    sc.vm[i] = vm;
-    sc.ivm[i] = 1.0 / vm;
-    s.vs[2 * i] = vr;
-    s.vs[2 * i + 1] = vi;
+  // V, |V|, 1/|V| at the given voltages (padding buses: V = 1)
+  {
+    const TxDev<double> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      double2 v;
+      v.x = 1.0;
+      v.y = 0.0;
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 16u;
+        v.x = bld<double>(V, e, 0);
+        v.y = bld<double>(V, e, 8);
+      }
+      const double vm = sqrt(v.x * v.x + v.y * v.y);
+      ws.st(VRE, k, v.x);
+      ws.st(VIM, k, v.y);
+      ws.st(VM, k, vm);
+      ws.st(IVM, k, 1.0 / vm);
+      s.vs[i] = v;
+    }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    double Ir = 0.0, Ii = 0.0;
-    for (int p = net.y_ptr[i]; p < net.y_ptr[i + 1]; ++p) {
-      const int c = net.y_col[p];
-      const double yr = net.y_re[p], yi = net.y_im[p], vr = s.vs[2 * c], vi = s.vs[2 * c + 1];
-      Ir += yr * vr - yi * vi;
-      Ii += yr * vi + yi * vr;
-    }
-    sc.ire[i] = Ir;
-    sc.iim[i] = Ii;
-  }
-  // dL/dx from the torch-convention gradient t = dL/dRe V + j dL/dIm V:
+  // I = Ybus V, and dL/dx from the torch-convention gradient t = dL/dRe V + j dL/dIm V:
   // dL/dtheta = Im(t) Re(V) - Re(t) Im(V), dL/d|V| = (Re(t) Re(V) + Im(t) Im(V)) / |V|
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (r < m) {
-      const int i = r < nth ? r : r - nth;
-      const double tr = tg[2 * ext[i]], ti = tg[2 * ext[i] + 1];
-      const double vr = V[2 * ext[i]], vi = V[2 * ext[i] + 1];
-      sc.F[r] = r < nth ? ti * vr - tr * vi : (tr * vr + ti * vi) / sqrt(vr * vr + vi * vi);
-    } else {
-      sc.F[r] = 0.0;
+  {
+    const TxDev<double> net = load_desc(netp);
+    double Ir[KB], Ii[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) Ir[k] = Ii[k] = 0.0;
+    sell_slots<KB, NW>(
+        net.y64,
+        [&](int k, double2 y, int c) {
+          const double2 v = s.vs[c];
+          Ir[k] += y.x * v.x - y.y * v.y;
+          Ii[k] += y.x * v.y + y.y * v.x;
+        },
+        [&](int) {});
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      ws.st(IRE, k, Ir[k]);
+      ws.st(IIM, k, Ii[k]);
+      double ft = 0.0, fv = 0.0;
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 16u;
+        const double tr = bld<double>(tg, e, 0), ti = bld<double>(tg, e, 8);
+        const double2 v = s.vs[i];
+        if ((int)i < nth) ft = ti * v.x - tr * v.y;
+        if ((int)i < npq) fv = (tr * v.x + ti * v.y) * ws.ld(IVM, k);
+      }
+      ws.st(FP, k, ft);
+      ws.st(FP, KB + k, fv);
     }
   }
   __syncthreads();
 
-  auto apply_jt = [&](double (&w)[K]) { vjp<BLOCK, K>(net, sc, kd, w, s.xs); };
-  auto apply_mt = [&](double (&w)[K]) { precond_t<BLOCK, K>(net, sc, kd, w, s.xs, s.tmp); };
-  const ByteModel bm{8.0 * m, 8.0 * m, 8.0 * n};
+  auto apply_jt = [&](double (&w)[K]) { vjp<BLOCK, KB>(netp, ws, w, s.xs); };
+  auto apply_mt = [&](double (&w)[K]) { precond_t<BLOCK, KB>(netp, ws, w, s); };
   double work = 0.0;
   bool ok;
-  const int its = gmres_solve<double, BLOCK, K>(apply_jt, apply_mt, sc.F, sc.dx, basis, mp, kd, R,
-                                                a.max_restarts, a.rtol, s, &ok, bm, &work);
-  double* gp = a.grad_p + (int64_t)b * a.ld;
-  double* gq = a.grad_q + (int64_t)b * a.ld;
-  // rows that carry no state (the slack's P, the Q of PV buses and the slack) are zero
-  for (int i = threadIdx.x; i < n; i += BLOCK) {
-    if (i >= nth) gp[ext[i]] = 0.0;
-    if (i >= npq) gq[ext[i]] = 0.0;
+  int its;
+  {
+    const TxDev<double> net = load_desc(netp);
+    const ByteModel bm{8.0 * net.m, 8.0 * net.m, 8.0 * n};
+    its = gmres_solve<double, BLOCK, KB>(apply_jt, apply_mt, ws, FP, DXP, basis, R, a.max_restarts, a.rtol, s,
+                                         &ok, bm, &work);
   }
-#pragma unroll 1
-  for (int k = 0; k < kd; ++k) {
-    const int r = (int)row<BLOCK>(k);
-    if (r < nth) gp[ext[r]] = sc.dx[r];
-    else if (r < m) gq[ext[r - nth]] = sc.dx[r];
+  const Buf gp = make_buf(a.grad_p + (int64_t)b * a.ld);
+  const Buf gq = make_buf(a.grad_q + (int64_t)b * a.ld);
+  // rows that carry no state (the slack's P, the Q of PV buses and the slack) are zero
+  {
+    const TxDev<double> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 8u;
+        bst(gp, (int)i < nth ? ws.ld(DXP, k) : 0.0, e, 0);
+        bst(gq, (int)i < npq ? ws.ld(DXP, KB + k) : 0.0, e, 0);
+      }
+    }
   }
   if (threadIdx.x == 0) {
     if (a.gmres_iters) a.gmres_iters[b] = its;
@@ -891,28 +1140,31 @@ __global__ __launch_bounds__(BLOCK) void adjoint_kernel(const TxDev<double>* __r
   }
 }
 
-// Shapes: BLOCK threads, K rows per thread, max(n, m) <= BLOCK * K.
+// Shapes: BLOCK threads, KB bus slots per thread, n <= BLOCK * KB.
 template <typename Launch>
-void dispatch_shape(int rows, Launch&& go) {
-  if (rows <= 64) go.template operator()<64, 1>();
-  else if (rows <= 256) go.template operator()<64, 4>();
-  else if (rows <= 1024) go.template operator()<256, 4>();
-  else if (rows <= 4096) go.template operator()<256, 16>();
-  else if (rows <= 16384) go.template operator()<512, 32>();
-  else fail(PF_INVALID_ARG, "networks above 16384 state rows are not supported");
+void dispatch_shape(int n, Launch&& go) {
+  if (n <= 64) go.template operator()<64, 1>();
+  else if (n <= 256) go.template operator()<64, 4>();
+  else if (n <= 1024) go.template operator()<256, 4>();
+  else if (n <= 2048) go.template operator()<256, 8>();
+  else if (n <= 4096) go.template operator()<512, 8>();
+  else if (n <= 8192) go.template operator()<1024, 8>();
+  else fail(PF_INVALID_ARG, "networks above 8192 buses are not supported");
 }
 
 struct ShapeOf {
   int* block;
-  template <int BLOCK, int K>
+  int* kb;
+  template <int BLOCK, int KB>
   void operator()() const {
     *block = BLOCK;
+    *kb = KB;
   }
 };
 
-size_t lds_bytes(const TxNetwork& net, int R, int block, int ts) {
+size_t lds_bytes(const TxNetwork& net, int R, int ts) {
   const int kmax = std::max(net.bp.host.k, net.bpp.host.k);
-  const NrLayout L = nr_layout(net.n, net.m, kmax, R, block / WAVE, ts);
+  const NrLayout L = nr_layout(net.nbp, net.nth, net.npq, kmax, R, net.block / WAVE, ts);
   if (L.total > 160 * 1024)
     fail(PF_INVALID_ARG, "network too large for the per-scenario LDS layout (" + std::to_string(L.total) +
                              " bytes)");
@@ -924,10 +1176,10 @@ struct NrGo {
   const TxNetwork& net;
   const NRLaunch& a;
   hipStream_t s;
-  template <int BLOCK, int K>
+  template <int BLOCK, int KB>
   void operator()() const {
-    const size_t lds = lds_bytes(net, a.restart, BLOCK, (int)sizeof(T));
-    auto kernel = nr_kernel<T, BLOCK, K>;
+    const size_t lds = lds_bytes(net, a.restart, (int)sizeof(T));
+    auto kernel = nr_kernel<T, BLOCK, KB>;
     if (lds > 64 * 1024)
       PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -940,10 +1192,10 @@ struct AdjGo {
   const TxNetwork& net;
   const AdjLaunch& a;
   hipStream_t s;
-  template <int BLOCK, int K>
+  template <int BLOCK, int KB>
   void operator()() const {
-    const size_t lds = lds_bytes(net, a.restart, BLOCK, 8);
-    auto kernel = adjoint_kernel<BLOCK, K>;
+    const size_t lds = lds_bytes(net, a.restart, 8);
+    auto kernel = adjoint_kernel<BLOCK, KB>;
     if (lds > 64 * 1024)
       PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -954,25 +1206,21 @@ struct AdjGo {
 
 }  // namespace
 
-int64_t nr_padded_rows(const TxNetwork& net) {
-  const int rows = std::max(net.n, net.m);
-  int block = 0;
-  dispatch_shape(rows, ShapeOf{&block});
-  return (int64_t)((rows + block - 1) / block) * block;
-}
-int64_t nr_ws_doubles(const TxNetwork& net) { return 7 * (int64_t)net.n + 2 * nr_padded_rows(net); }
+void nr_shape(int n, int* block, int* kb) { dispatch_shape(n, ShapeOf{block, kb}); }
+
+int64_t nr_padded_rows(const TxNetwork& net) { return 2 * (int64_t)net.nbp; }
+int64_t nr_ws_doubles(const TxNetwork& net) { return 13 * (int64_t)net.nbp; }
 int64_t adj_ws_doubles(const TxNetwork& net) { return nr_ws_doubles(net); }
 
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s) {
   if (a.batch == 0) return;
-  const int rows = std::max(net.n, net.m);
-  if (mixed) dispatch_shape(rows, NrGo<float>{net, a, s});
-  else dispatch_shape(rows, NrGo<double>{net, a, s});
+  if (mixed) dispatch_shape(net.n, NrGo<float>{net, a, s});
+  else dispatch_shape(net.n, NrGo<double>{net, a, s});
 }
 
 void launch_adjoint(const TxNetwork& net, const AdjLaunch& a, hipStream_t s) {
   if (a.batch == 0) return;
-  dispatch_shape(std::max(net.n, net.m), AdjGo{net, a, s});
+  dispatch_shape(net.n, AdjGo{net, a, s});
 }
 
 // ---------------------------------------------------------------------------
@@ -983,7 +1231,7 @@ void launch_adjoint(const TxNetwork& net, const AdjLaunch& a, hipStream_t s) {
 __global__ __launch_bounds__(256) void branch_loss_kernel(const TxDev<double>* __restrict__ netp,
                                                           const int* inc_ptr, const int* inc_br, LossLaunch a) {
   __shared__ double red[4];
-  const TxDev<double>& net = *netp;
+  const TxDev<double> net = load_desc(netp);
   const int b = blockIdx.x;
   const double* v = a.v + 2 * (int64_t)b * a.ld;
   const int* ext = net.int2ext;

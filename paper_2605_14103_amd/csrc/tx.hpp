@@ -2,10 +2,13 @@
 // Newton-Raphson, branch-loss and adjoint kernels take by value.
 //
 // Internal bus order.  Buses are renumbered so that PQ buses come first, then
-// PV buses, then the slack.  With n buses, nth = n - 1 and npq PQ buses, the
-// Newton state x = [theta over Theta ; |V| over Q] (eq. (1)) then has row r <
-// nth for the angle of internal bus r and row nth + q for the magnitude of
-// internal bus q < npq: no index maps are needed inside the kernels.
+// PV buses, then the slack (each group by decreasing degree, so that rows of
+// similar length share a slice).  With n buses, nth = n - 1 and npq PQ buses,
+// Theta is internal buses 0..nth-1 and Q is 0..npq-1.  The kernels hold the
+// Newton state x = [theta over Theta ; |V| over Q] (eq. (1)) bus-major: two
+// planes of nbp (padded bus count) entries, angle of bus i at i and magnitude
+// of bus i at nbp + i, zero where a bus carries no such state.  A thread owns
+// buses t + k block (k < kb) and both of their entries.
 #pragma once
 
 #include <cstdint>
@@ -16,45 +19,59 @@
 
 namespace pfx {
 
-// Device view of one HybridFactor (see factor.hpp), values in T.
+// Sliced ELLPACK: rows are grouped in slices of 64 (one wavefront), each
+// slice padded to its longest row.  Entry p of the row on lane l of slice s
+// sits at off[s] + 64 p + l; padding entries have column 0 and value 0.
+template <typename V>
+struct Sell {
+  const int* off;     // [n_slices]
+  const int* width;   // [n_slices]
+  const int* col;
+  const V* val;
+};
+
 template <typename T>
-struct SpdDev {
-  int N, c, k, nfl, nbl;
-  const int* pinv;
-  const int* f_lev;
-  const int* f_rows;
-  const int* L_ptr;
-  const int* L_col;
-  const T* L_val;
-  const T* dinv;
-  const int* b_lev;
-  const int* b_rows;
-  const int* T_ptr;
-  const int* T_col;
-  const T* T_val;
-  const T* Sinv;
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
+// Device view of one explicit factor (factor.hpp, ExplicitFactor) laid out for
+// one workgroup of `block` threads.
+//   E1: rows sorted by length into slices; slice lists per wave (at most kb
+//       slices each, resolved to entry offset and width), row ids per lane
+//       (factor position, -1 for none); input
+//       columns are positions of the matrix order (the permutation is folded in).
+//   E3: one row per matrix row i (bus order), slices = consecutive 64 rows;
+//       columns are factor positions.
+template <typename T>
+struct EfDev {
+  int N, c, k;
+  Sell<T> e1;
+  const int* e1_row;     // [n_slices * 64]
+  const int* e1_wave;    // [n_waves * kb][4]: entry offset, width, first row id index, 0
+  Sell<T> e3;
+  const T* sinv;         // k x k, column-major (symmetric)
 };
 
 template <typename T>
 struct TxDev {
   int n, nth, npq, m;
-  const int* y_ptr;      // Ybus CSR in internal order
-  const int* y_col;
-  const double* y_re;
-  const double* y_im;
+  int kb;                // bus slots per thread
+  int nbp;               // padded bus count, kb * block
   const int* int2ext;    // internal bus -> caller's bus index
-  SpdDev<T> bp;          // (B' + eps I)^-1 over Theta
-  SpdDev<T> bpp;         // (B'' + eps I)^-1 over Q
-  const int* g_ptr;      // G = -Re(Ybus)[Q, Theta]; columns as factor positions of bp
-  const int* g_col;
-  const T* g_val;
-  const int* gt_ptr;     // G^T; rows Theta, columns as factor positions of bpp
-  const int* gt_col;
-  const T* gt_val;
-  const int* yt_ptr;     // Ybus^T CSR (internal order), for the adjoint
-  const int* yt_col;
-  const double* yt_re;
-  const double* yt_im;
+  Sell<double2> y64;     // Ybus rows by internal bus (FP64 values)
+  Sell<typename Vec2<T>::type> yT;   // the same entries in T (Jacobian-vector products)
+  Sell<double2> yt;      // Ybus^T rows (adjoint)
+  Sell<T> g;             // G = -Re(Ybus)[Q, Theta]: rows PQ buses, columns Theta buses
+  Sell<double> gt;       // G^T: rows Theta buses, columns PQ buses (adjoint)
+  EfDev<T> bp;           // (B' + eps I)^-1 over Theta
+  EfDev<T> bpp;          // (B'' + eps I)^-1 over Q
   // branch list (internal bus numbers) for the branch-current loss
   int n_branch;
   const int* br_f;
@@ -64,25 +81,32 @@ struct TxDev {
   const double* br_b;
 };
 
-// Device copies of one factor: index arrays once, values in FP64 and FP32.
-struct SpdBuffers {
-  HybridFactor host;
-  DeviceBuffer pinv, f_lev, f_rows, L_ptr, L_col, b_lev, b_rows, T_ptr, T_col;
-  DeviceBuffer L_val64, dinv64, T_val64, Sinv64;
-  DeviceBuffer L_val32, dinv32, T_val32, Sinv32;
+// Host-built sliced ELLPACK with device copies of its values in FP64 and FP32.
+struct SellBuffers {
+  int n_slices = 0;
+  long entries = 0;
+  DeviceBuffer off, width, col, val64, val32;
+  template <typename V>
+  Sell<V> view() const;
+};
+
+struct EfBuffers {
+  ExplicitFactor host;
+  SellBuffers e1, e3;
+  DeviceBuffer e1_row, e1_wave, sinv64, sinv32;
   template <typename T>
-  SpdDev<T> view() const;
+  EfDev<T> view() const;
 };
 
 struct TxNetwork {
   Context* ctx = nullptr;
   int n = 0, nth = 0, npq = 0, m = 0, nnz = 0, n_branch = 0;
+  int block = 0, kb = 0, nbp = 0;   // workgroup shape of the solve kernels
   std::vector<int> int2ext, ext2int;
   pf_opts setup{};
-  DeviceBuffer y_ptr, y_col, y_re, y_im, int2ext_d;
-  DeviceBuffer yt_ptr, yt_col, yt_re, yt_im;   // Ybus^T (internal order) for the adjoint
-  SpdBuffers bp, bpp;
-  DeviceBuffer g_ptr, g_col, g_val64, g_val32, gt_ptr, gt_col, gt_val64, gt_val32;
+  DeviceBuffer int2ext_d;
+  SellBuffers y, yt, g, gt;   // y/yt values are complex (re, im pairs)
+  EfBuffers bp, bpp;
   DeviceBuffer br_f, br_t, br_ys_re, br_ys_im, br_b;
   DeviceBuffer inc_ptr, inc_br;   // branches incident to each internal bus
   // solve workspaces (grow-only); calls on one network must not overlap
@@ -96,6 +120,10 @@ struct TxNetwork {
     return sizeof(T) == 8 ? desc64.as<const TxDev<T>>() : desc32.as<const TxDev<T>>();
   }
 };
+
+// Workgroup shape for a network of n buses: block threads, kb bus slots per
+// thread (n <= kb * block).
+void nr_shape(int n, int* block, int* kb);
 
 // Launchers (nr_kernels.hip).
 struct NRLaunch {
@@ -119,7 +147,7 @@ struct NRLaunch {
 };
 
 // Doubles of per-scenario FP64 workspace the NR kernel needs, and the padded
-// state length (rows per thread times threads) of its vectors.
+// state length (2 nbp: an angle plane and a magnitude plane) of its vectors.
 int64_t nr_ws_doubles(const TxNetwork& net);
 int64_t nr_padded_rows(const TxNetwork& net);
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s);

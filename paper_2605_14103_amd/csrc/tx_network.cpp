@@ -1,10 +1,13 @@
 // Transmission network registration: index sets, internal ordering, the
-// preconditioner blocks of eq. (7) and their precomputed inverses.
+// preconditioner blocks of eq. (7) with their precomputed inverses, and the
+// sliced layouts the kernels read.
 #include <algorithm>
 #include <cmath>
 #include <complex>
 #include <map>
+#include <numeric>
 #include <string>
+#include <tuple>
 
 #include "tx.hpp"
 
@@ -12,30 +15,123 @@ namespace pfx {
 
 namespace {
 
-template <typename T>
-std::vector<T> cast_vec(const std::vector<double>& v) {
-  return std::vector<T>(v.begin(), v.end());
+constexpr int SLICE = 64;
+
+using Entry = std::tuple<int, double, double>;   // column, value (re), value (im)
+using Row = std::vector<Entry>;
+
+struct SellHost {
+  std::vector<int> off, width, col;
+  std::vector<double> re, im;
+  long entries = 0;
+};
+
+// Rows (a multiple of 64 of them) into slices of 64 consecutive rows.  Each
+// slice's width is at least 1 and a multiple of `quantum` (padding entries are
+// zeros), so that kernels may read a slice's last entry unconditionally and
+// unroll by the quantum without a remainder.
+SellHost build_sell(const std::vector<Row>& rows, int quantum = 1) {
+  SellHost h;
+  const int ns = (int)rows.size() / SLICE;
+  h.off.resize(ns);
+  h.width.resize(ns);
+  int cur = 0;
+  for (int s = 0; s < ns; ++s) {
+    int w = 1;
+    for (int l = 0; l < SLICE; ++l) w = std::max(w, (int)rows[s * SLICE + l].size());
+    w = (w + quantum - 1) / quantum * quantum;
+    h.off[s] = cur;
+    h.width[s] = w;
+    cur += SLICE * w;
+  }
+  h.col.assign(cur, 0);
+  h.re.assign(cur, 0.0);
+  h.im.assign(cur, 0.0);
+  for (int s = 0; s < ns; ++s)
+    for (int l = 0; l < SLICE; ++l) {
+      const Row& r = rows[s * SLICE + l];
+      for (size_t p = 0; p < r.size(); ++p) {
+        const int q = h.off[s] + (int)p * SLICE + l;
+        h.col[q] = std::get<0>(r[p]);
+        h.re[q] = std::get<1>(r[p]);
+        h.im[q] = std::get<2>(r[p]);
+      }
+      h.entries += (long)r.size();
+    }
+  return h;
 }
 
-void upload_factor(Context* ctx, SpdBuffers& s) {
-  const HybridFactor& F = s.host;
-  s.pinv = upload(ctx, F.pinv);
-  s.f_lev = upload(ctx, F.f_lev);
-  s.f_rows = upload(ctx, F.f_rows);
-  s.L_ptr = upload(ctx, F.L_ptr);
-  s.L_col = upload(ctx, F.L_col);
-  s.b_lev = upload(ctx, F.b_lev);
-  s.b_rows = upload(ctx, F.b_rows);
-  s.T_ptr = upload(ctx, F.T_ptr);
-  s.T_col = upload(ctx, F.T_col);
-  s.L_val64 = upload(ctx, F.L_val);
-  s.dinv64 = upload(ctx, F.dinv);
-  s.T_val64 = upload(ctx, F.T_val);
-  s.Sinv64 = upload(ctx, F.Sinv);
-  s.L_val32 = upload(ctx, cast_vec<float>(F.L_val));
-  s.dinv32 = upload(ctx, cast_vec<float>(F.dinv));
-  s.T_val32 = upload(ctx, cast_vec<float>(F.T_val));
-  s.Sinv32 = upload(ctx, cast_vec<float>(F.Sinv));
+void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b) {
+  b.n_slices = (int)h.off.size();
+  b.entries = h.entries;
+  b.off = upload(ctx, h.off);
+  b.width = upload(ctx, h.width);
+  b.col = upload(ctx, h.col);
+  if (cplx) {
+    std::vector<double> v64(2 * h.re.size());
+    std::vector<float> v32(2 * h.re.size());
+    for (size_t i = 0; i < h.re.size(); ++i) {
+      v64[2 * i] = h.re[i];
+      v64[2 * i + 1] = h.im[i];
+      v32[2 * i] = (float)h.re[i];
+      v32[2 * i + 1] = (float)h.im[i];
+    }
+    b.val64 = upload(ctx, v64);
+    b.val32 = upload(ctx, v32);
+  } else {
+    b.val64 = upload(ctx, h.re);
+    b.val32 = upload(ctx, std::vector<float>(h.re.begin(), h.re.end()));
+  }
+}
+
+// Lay out one explicit factor for workgroups of `block` threads with kb bus
+// slots each (the factor order has N <= kb * block rows).
+void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
+  const ExplicitFactor& E = f.host;
+  const int N = E.N, nw = block / SLICE;
+  // E1: rows by decreasing length, columns in matrix order.
+  std::vector<int> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return E.e1[a].size() > E.e1[b].size(); });
+  const int ns1 = (N + SLICE - 1) / SLICE;
+  std::vector<Row> rows1((size_t)ns1 * SLICE);
+  std::vector<int> rid((size_t)ns1 * SLICE, -1);
+  for (int q = 0; q < N; ++q) {
+    const int r = order[q];
+    rid[q] = r;
+    for (auto [j, v] : E.e1[r]) rows1[q].push_back({E.perm[j], v, 0.0});
+  }
+  SellHost h1 = build_sell(rows1, 4);
+  // Slices to waves: longest first, each to the least loaded wave with room.
+  std::vector<int> sl(ns1);
+  std::iota(sl.begin(), sl.end(), 0);
+  std::stable_sort(sl.begin(), sl.end(), [&](int a, int b) { return h1.width[a] > h1.width[b]; });
+  // Per wave and slot: (entry offset, width, first row of the slice, 0);
+  // width 0 past the wave's list.
+  std::vector<int> load(nw, 0), cnt(nw, 0), wave_list((size_t)nw * kb * 4, 0);
+  for (int s : sl) {
+    int best = -1;
+    for (int w = 0; w < nw; ++w)
+      if (cnt[w] < kb && (best < 0 || load[w] < load[best])) best = w;
+    if (best < 0) fail(PF_INVALID_ARG, "factor does not fit the workgroup layout");
+    int* e = &wave_list[((size_t)best * kb + cnt[best]++) * 4];
+    e[0] = h1.off[s];
+    e[1] = h1.width[s];
+    e[2] = s * SLICE;
+    load[best] += h1.width[s];
+  }
+  // E3: one row per matrix row (bus order), padded to nbp rows.
+  std::vector<Row> rows3(nbp);
+  for (int i = 0; i < N; ++i)
+    for (auto [p, v] : E.e3[E.pinv[i]]) rows3[i].push_back({p, v, 0.0});
+  SellHost h3 = build_sell(rows3, 4);
+  upload_sell(ctx, h1, false, f.e1);
+  upload_sell(ctx, h3, false, f.e3);
+  f.e1_row = upload(ctx, rid);
+  f.e1_wave = upload(ctx, wave_list);
+  f.sinv64 = upload(ctx, E.Sinv);
+  f.sinv32 = upload(ctx, std::vector<float>(E.Sinv.begin(), E.Sinv.end()));
 }
 
 // A principal submatrix of -Im(Y) (rows/cols 0..k-1 of the internal order) plus eps I.
@@ -68,11 +164,11 @@ SparseSym leading_block(const std::vector<int>& ptr, const std::vector<int>& col
   return A;
 }
 
-void check_factor(const SparseSym& A, const HybridFactor& F, const char* name) {
+void check_factor(const SparseSym& A, const ExplicitFactor& F, const char* name) {
   // Set-up self-check: solve against a fixed right-hand side and verify the residual.
   std::vector<double> b(A.n);
   for (int i = 0; i < A.n; ++i) b[i] = 1.0 + 0.25 * std::sin(0.7 * i);
-  std::vector<double> x = hybrid_solve(F, b);
+  std::vector<double> x = explicit_solve(F, b);
   // Backward-error test: |b - A x| against |A| |x| + |b| (the matrix may be indefinite).
   double rmax = 0.0, scale = 0.0;
   for (int i = 0; i < A.n; ++i) {
@@ -90,67 +186,66 @@ void check_factor(const SparseSym& A, const HybridFactor& F, const char* name) {
 
 }  // namespace
 
+template <>
+Sell<double> SellBuffers::view<double>() const {
+  return Sell<double>{off.as<int>(), width.as<int>(), col.as<int>(), val64.as<double>()};
+}
+template <>
+Sell<float> SellBuffers::view<float>() const {
+  return Sell<float>{off.as<int>(), width.as<int>(), col.as<int>(), val32.as<float>()};
+}
+template <>
+Sell<double2> SellBuffers::view<double2>() const {
+  return Sell<double2>{off.as<int>(), width.as<int>(), col.as<int>(), val64.as<double2>()};
+}
+template <>
+Sell<float2> SellBuffers::view<float2>() const {
+  return Sell<float2>{off.as<int>(), width.as<int>(), col.as<int>(), val32.as<float2>()};
+}
+
 template <typename T>
-SpdDev<T> SpdBuffers::view() const {
+EfDev<T> EfBuffers::view() const {
   constexpr bool f64 = sizeof(T) == 8;
-  SpdDev<T> d;
+  EfDev<T> d;
   d.N = host.N;
   d.c = host.c;
   d.k = host.k;
-  d.nfl = host.n_fwd_levels();
-  d.nbl = host.n_bwd_levels();
-  d.pinv = pinv.as<int>();
-  d.f_lev = f_lev.as<int>();
-  d.f_rows = f_rows.as<int>();
-  d.L_ptr = L_ptr.as<int>();
-  d.L_col = L_col.as<int>();
-  d.L_val = f64 ? L_val64.as<T>() : L_val32.as<T>();
-  d.dinv = f64 ? dinv64.as<T>() : dinv32.as<T>();
-  d.b_lev = b_lev.as<int>();
-  d.b_rows = b_rows.as<int>();
-  d.T_ptr = T_ptr.as<int>();
-  d.T_col = T_col.as<int>();
-  d.T_val = f64 ? T_val64.as<T>() : T_val32.as<T>();
-  d.Sinv = f64 ? Sinv64.as<T>() : Sinv32.as<T>();
+  d.e1 = e1.view<T>();
+  d.e1_row = e1_row.as<int>();
+  d.e1_wave = e1_wave.as<int>();
+  d.e3 = e3.view<T>();
+  d.sinv = f64 ? sinv64.as<T>() : sinv32.as<T>();
   return d;
 }
 
 template <typename T>
 TxDev<T> TxNetwork::view() const {
-  constexpr bool f64 = sizeof(T) == 8;
   TxDev<T> d;
   d.n = n;
   d.nth = nth;
   d.npq = npq;
   d.m = m;
-  d.y_ptr = y_ptr.as<int>();
-  d.y_col = y_col.as<int>();
-  d.y_re = y_re.as<double>();
-  d.y_im = y_im.as<double>();
+  d.kb = kb;
+  d.nbp = nbp;
   d.int2ext = int2ext_d.as<int>();
+  d.y64 = y.view<double2>();
+  d.yT = y.view<typename Vec2<T>::type>();
+  d.yt = yt.view<double2>();
+  d.g = g.view<T>();
+  d.gt = gt.view<double>();
   d.bp = bp.view<T>();
   d.bpp = bpp.view<T>();
-  d.g_ptr = g_ptr.as<int>();
-  d.g_col = g_col.as<int>();
-  d.g_val = f64 ? g_val64.as<T>() : g_val32.as<T>();
-  d.gt_ptr = gt_ptr.as<int>();
-  d.gt_col = gt_col.as<int>();
-  d.gt_val = f64 ? gt_val64.as<T>() : gt_val32.as<T>();
   d.n_branch = n_branch;
   d.br_f = br_f.as<int>();
   d.br_t = br_t.as<int>();
   d.br_ys_re = br_ys_re.as<double>();
   d.br_ys_im = br_ys_im.as<double>();
   d.br_b = br_b.as<double>();
-  d.yt_ptr = yt_ptr.as<int>();
-  d.yt_col = yt_col.as<int>();
-  d.yt_re = yt_re.as<double>();
-  d.yt_im = yt_im.as<double>();
   return d;
 }
 
-template SpdDev<double> SpdBuffers::view<double>() const;
-template SpdDev<float> SpdBuffers::view<float>() const;
+template EfDev<double> EfBuffers::view<double>() const;
+template EfDev<float> EfBuffers::view<float>() const;
 template TxDev<double> TxNetwork::view<double>() const;
 template TxDev<float> TxNetwork::view<float>() const;
 
@@ -177,11 +272,17 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
     }
   }
   require(n_slack == 1, "exactly one slack bus is required");
+  std::vector<int> degree(n_bus, 0);
   for (int i = 0; i < n_bus; ++i) {
     require(row_ptr[i + 1] >= row_ptr[i], "row_ptr must be non-decreasing");
-    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
       require(col_idx[p] >= 0 && col_idx[p] < n_bus, "column index out of range");
+      if (col_idx[p] != i) ++degree[i];
+    }
   }
+  auto by_degree = [&](int a, int b) { return degree[a] != degree[b] ? degree[a] > degree[b] : a < b; };
+  std::sort(pq.begin(), pq.end(), by_degree);
+  std::sort(pv.begin(), pv.end(), by_degree);
 
   auto net = std::make_unique<TxNetwork>();
   net->ctx = ctx;
@@ -196,6 +297,9 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
   net->int2ext.push_back(slack);
   net->ext2int.assign(n_bus, 0);
   for (int i = 0; i < n_bus; ++i) net->ext2int[net->int2ext[i]] = i;
+  nr_shape(n_bus, &net->block, &net->kb);
+  net->nbp = net->block * net->kb;
+  const int nbp = net->nbp, nth = net->nth, npq = net->npq;
 
   // Ybus in internal order, duplicates summed, columns sorted.
   std::vector<int> ptr(n_bus + 1, 0), col;
@@ -216,78 +320,38 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
 
   // B' = -Im(Y)[Theta, Theta] + eps I, B'' = -Im(Y)[Q, Q] + eps I (eqs. (7)-(9)).
   const double eps = setup.eps;
-  SparseSym Bp = leading_block(ptr, col, yim, net->nth, eps);
-  SparseSym Bpp = leading_block(ptr, col, yim, net->npq, eps);
+  SparseSym Bp = leading_block(ptr, col, yim, nth, eps);
+  SparseSym Bpp = leading_block(ptr, col, yim, npq, eps);
   if (setup.precond_block > 0) {
     Bp = block_diagonal_part(Bp, setup.precond_block);
     Bpp = block_diagonal_part(Bpp, setup.precond_block);
   }
-  net->bp.host = hybrid_factor(Bp, setup.factor_max_levels, setup.factor_max_core);
+  net->bp.host = explicit_factor(Bp, setup.factor_max_levels, setup.factor_max_core, net->block);
   check_factor(Bp, net->bp.host, "B'");
-  if (net->npq > 0) {
-    net->bpp.host = hybrid_factor(Bpp, setup.factor_max_levels, setup.factor_max_core);
+  upload_factor(ctx, net->bp, net->block, net->kb, nbp);
+  if (npq > 0) {
+    net->bpp.host = explicit_factor(Bpp, setup.factor_max_levels, setup.factor_max_core, net->block);
     check_factor(Bpp, net->bpp.host, "B''");
+    upload_factor(ctx, net->bpp, net->block, net->kb, nbp);
   }
 
-  // G = -Re(Y)[Q, Theta] with columns as positions of the B' factor, and G^T
-  // with columns as positions of the B'' factor.
-  std::vector<int> gptr(net->npq + 1, 0), gcol;
-  std::vector<double> gval;
-  std::vector<std::vector<std::pair<int, double>>> gt_rows(net->nth);
-  for (int q = 0; q < net->npq; ++q) {
-    for (int p = ptr[q]; p < ptr[q + 1]; ++p) {
-      int j = col[p];
-      if (j >= net->nth) continue;
-      double g = -yre[p];
-      gcol.push_back(net->bp.host.pinv[j]);
-      gval.push_back(g);
-      gt_rows[j].push_back({net->bpp.host.pinv.empty() ? 0 : net->bpp.host.pinv[q], g});
-    }
-    gptr[q + 1] = (int)gcol.size();
-  }
-  std::vector<int> gtptr(net->nth + 1, 0), gtcol;
-  std::vector<double> gtval;
-  for (int j = 0; j < net->nth; ++j) {
-    for (auto [c, v] : gt_rows[j]) {
-      gtcol.push_back(c);
-      gtval.push_back(v);
-    }
-    gtptr[j + 1] = (int)gtcol.size();
-  }
-
-  net->y_ptr = upload(ctx, ptr);
-  net->y_col = upload(ctx, col);
-  net->y_re = upload(ctx, yre);
-  net->y_im = upload(ctx, yim);
-  net->int2ext_d = upload(ctx, net->int2ext);
-  {
-    std::vector<int> tp(n_bus + 1, 0), tc(col.size());
-    std::vector<double> tr(col.size()), ti(col.size());
-    for (int j : col) tp[j + 1]++;
-    for (int i = 0; i < n_bus; ++i) tp[i + 1] += tp[i];
-    std::vector<int> fill(tp.begin(), tp.end() - 1);
-    for (int i = 0; i < n_bus; ++i)
-      for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
-        const int q = fill[col[p]]++;
-        tc[q] = i;
-        tr[q] = yre[p];
-        ti[q] = yim[p];
+  // Sliced layouts by internal bus: Ybus, Ybus^T, G = -Re(Y)[Q, Theta] and G^T.
+  std::vector<Row> yr(nbp), ytr(nbp), gr(nbp), gtr(nbp);
+  for (int i = 0; i < n_bus; ++i)
+    for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+      const int j = col[p];
+      yr[i].push_back({j, yre[p], yim[p]});
+      ytr[j].push_back({i, yre[p], yim[p]});
+      if (i < npq && j < nth) {
+        gr[i].push_back({j, -yre[p], 0.0});
+        gtr[j].push_back({i, -yre[p], 0.0});
       }
-    net->yt_ptr = upload(ctx, tp);
-    net->yt_col = upload(ctx, tc);
-    net->yt_re = upload(ctx, tr);
-    net->yt_im = upload(ctx, ti);
-  }
-  upload_factor(ctx, net->bp);
-  if (net->npq > 0) upload_factor(ctx, net->bpp);
-  net->g_ptr = upload(ctx, gptr);
-  net->g_col = upload(ctx, gcol);
-  net->g_val64 = upload(ctx, gval);
-  net->g_val32 = upload(ctx, cast_vec<float>(gval));
-  net->gt_ptr = upload(ctx, gtptr);
-  net->gt_col = upload(ctx, gtcol);
-  net->gt_val64 = upload(ctx, gtval);
-  net->gt_val32 = upload(ctx, cast_vec<float>(gtval));
+    }
+  upload_sell(ctx, build_sell(yr, 4), true, net->y);
+  upload_sell(ctx, build_sell(ytr, 4), true, net->yt);
+  upload_sell(ctx, build_sell(gr, 4), false, net->g);
+  upload_sell(ctx, build_sell(gtr, 4), false, net->gt);
+  net->int2ext_d = upload(ctx, net->int2ext);
 
   std::vector<int> bf(n_branch), bt(n_branch);
   std::vector<double> ysr(n_branch), ysi(n_branch), bb(n_branch);
