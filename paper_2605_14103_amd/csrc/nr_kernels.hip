@@ -25,9 +25,9 @@
 //             Jacobian-vector products dS = dV conj(I) + V conj(Ybus dV),
 //             dV = V (j dtheta + d|V| / |V|), the preconditioner applied by the
 //             forward block substitution of eqs. (8)-(9) with explicit factor
-//             passes, classical Gram-Schmidt with a second pass whenever the
-//             first cancels more than half of the squared norm (Kahan-Parlett),
-//             Givens rotations on the Hessenberg matrix
+//             passes, classical Gram-Schmidt with a second pass when the first
+//             cancels all but 1/64 of the norm, Givens rotations on the
+//             Hessenberg matrix
 //   update    theta += dx_theta, |V| += dx_|V|   (FP64)
 #include <hip/hip_runtime.h>
 
@@ -250,7 +250,7 @@ __host__ __device__ inline NrLayout nr_layout(int nbp, int nth, int npq, int kma
   // the preconditioner runs (each phase in between ends with a barrier).
   const int red_bytes = 2 * (R + 2) * NW * 8;
   L.red = o;  o += align16(red_bytes);
-  const int tmp_bytes = (kmax > 0 ? kmax : 1) * ts;
+  const int tmp_bytes = ((kmax > 0 ? kmax : 1) + 3) / 4 * 4 * ts;   // whole packs of the dense core
   if (tmp_bytes <= red_bytes) {
     L.tmp = L.red;
   } else {
@@ -441,18 +441,39 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
       else if (r >= 0) aux[r] = acc;
     }
   }
+  {  // the dense core reads whole packs: zero the core right-hand side past k
+    constexpr int P = 16 / (int)sizeof(T);
+    const int pad = (f.k + P - 1) / P * P - f.k;
+    if ((int)threadIdx.x < pad) tmp[f.k + threadIdx.x] = 0;
+  }
   __syncthreads();
+  // S^-1 is stored in packs of P = 16 / sizeof(T) consecutive columns per row
+  // ([l / P][i][P], zero-padded), so each lane reads P entries with one
+  // 16-byte load.
+  constexpr int P = 16 / (int)sizeof(T);
+  const int kp = (f.k + P - 1) / P;
   for (int i = threadIdx.x; i < f.k; i += BLOCK) {
     T acc[4] = {0, 0, 0, 0};
-    int l = 0;
-    for (; l + 15 < f.k; l += 16) {
-      T v[16];
+    int lp = 0;
+    for (; lp + 7 < kp; lp += 8) {
+      int4 v[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = cld(f.sinv, (unsigned)((l + u) * f.k + i));
+      for (int u = 0; u < 8; ++u) v[u] = cld(reinterpret_cast<const int4*>(f.sinv), (unsigned)((lp + u) * f.k + i));
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc[u & 3] += v[u] * tmp[l + u];
+      for (int u = 0; u < 8; ++u) {
+        T e[P];
+        __builtin_memcpy(e, &v[u], 16);
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q & 3] += e[q] * tmp[(lp + u) * P + q];
+      }
     }
-    for (; l < f.k; ++l) acc[0] += cld(f.sinv, (unsigned)(l * f.k + i)) * tmp[l];
+    for (; lp < kp; ++lp) {
+      const int4 v = cld(reinterpret_cast<const int4*>(f.sinv), (unsigned)(lp * f.k + i));
+      T e[P];
+      __builtin_memcpy(e, &v, 16);
+#pragma unroll
+      for (int q = 0; q < P; ++q) acc[q & 3] += e[q] * tmp[lp * P + q];
+    }
     aux[f.c + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
   __syncthreads();
@@ -684,9 +705,9 @@ struct ByteModel {
 // the tolerance was met.
 //
 // Orthogonalisation runs on w = A v_j - v_j (see below).  One reduction gives
-// <v_i, w> and ||w||^2 together, and
-// ||w'||^2 = ||w||^2 - sum h_i^2 after the projection; a second pass runs when
-// that cancels more than half of ||w||^2.  Every thread applies the Givens
+// <v_i, w> and ||w||^2 together, and ||w'||^2 = ||w||^2 - sum h_i^2 after the
+// projection; a second classical Gram-Schmidt pass runs when that leaves less
+// than 1/64 of the norm.  Every thread applies the Givens
 // rotations to the new Hessenberg column itself (same data, same operations),
 // so no barrier is needed after them; thread 0 alone stores H, the rotations
 // and the rotated right-hand side for later steps.
@@ -756,8 +777,11 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
       const T hh1 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
       const T wn2 = part_sum<T, NW>(p1, j + 1);
       T nrm2 = wn2 - hh1;
-      // second pass when the first removed more than half of the squared norm
-      const bool again = nrm2 < (T)0.5 * wn2;
+      // Second pass only when the projection removed all but 1/64 of the
+      // norm: the first pass's rounding then leaves the new vector orthogonal
+      // to about 64 ulp, far below the GMRES tolerance, and a pass is saved in
+      // most steps.
+      const bool again = nrm2 < (T)(1.0 / 4096.0) * wn2;
       T* p2 = p1;
       if (again) {
         T s1 = 0;

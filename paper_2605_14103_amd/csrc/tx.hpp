@@ -56,7 +56,7 @@ struct EfDev {
   const int* e1_row;     // [n_slices * 64]
   const int* e1_wave;    // [n_waves * kb][4]: entry offset, width, first row id index, 0
   Sell<T> e3;
-  const T* sinv;         // k x k, column-major (symmetric)
+  const T* sinv;         // S^-1 (k x k) in packs [l / P][i][P], P = 16 / sizeof(T)
 };
 
 template <typename T>

@@ -107,6 +107,8 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
   std::vector<int> sl(ns1);
   std::iota(sl.begin(), sl.end(), 0);
   std::stable_sort(sl.begin(), sl.end(), [&](int a, int b) { return h1.width[a] > h1.width[b]; });
+  // (the slice list is longest first, so the greedy assignment balances the
+  // longest slices first)
   // Per wave and slot: (entry offset, width, first row of the slice, 0);
   // width 0 past the wave's list.
   std::vector<int> load(nw, 0), cnt(nw, 0), wave_list((size_t)nw * kb * 4, 0);
@@ -119,7 +121,7 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
     e[0] = h1.off[s];
     e[1] = h1.width[s];
     e[2] = s * SLICE;
-    load[best] += h1.width[s];
+    load[best] += h1.width[s] / 4 + 1;   // rounds of four entries, plus the slice's own overhead
   }
   // E3: one row per matrix row (bus order), padded to nbp rows.
   std::vector<Row> rows3(nbp);
@@ -130,8 +132,23 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
   upload_sell(ctx, h3, false, f.e3);
   f.e1_row = upload(ctx, rid);
   f.e1_wave = upload(ctx, wave_list);
-  f.sinv64 = upload(ctx, E.Sinv);
-  f.sinv32 = upload(ctx, std::vector<float>(E.Sinv.begin(), E.Sinv.end()));
+  // S^-1 in packs of P columns per row, [l / P][i][P], zero-padded (P = 2 in
+  // FP64, 4 in FP32: one 16-byte load per pack)
+  const int k = E.k;
+  auto packed = [&](int P) {
+    const int kp = (k + P - 1) / P;
+    std::vector<double> out((size_t)std::max(1, kp * k * P), 0.0);
+    for (int lp = 0; lp < kp; ++lp)
+      for (int i = 0; i < k; ++i)
+        for (int q = 0; q < P; ++q) {
+          const int l = lp * P + q;
+          if (l < k) out[((size_t)lp * k + i) * P + q] = E.Sinv[(size_t)l * k + i];
+        }
+    return out;
+  };
+  f.sinv64 = upload(ctx, packed(2));
+  const std::vector<double> s4 = packed(4);
+  f.sinv32 = upload(ctx, std::vector<float>(s4.begin(), s4.end()));
 }
 
 // A principal submatrix of -Im(Y) (rows/cols 0..k-1 of the internal order) plus eps I.
