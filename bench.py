@@ -112,6 +112,32 @@ def time_steps(fn, steps: int, warmup: int):
     return ms, wall, out
 
 
+TRAFFIC_SOURCES = ("paper_2605_14103_amd/csrc/nr_kernels.hip", "paper_2605_14103_amd/csrc/tx_network.cpp",
+                   "paper_2605_14103_amd/csrc/factor.cpp")
+
+
+def measured_traffic(profile: str, key: str) -> float | None:
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("TRAFFIC_JSON "):
+            rec = json.loads(line[len("TRAFFIC_JSON "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+        return None
+    return rec.get(key)
+
+
 def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
     import torch
 
@@ -162,8 +188,11 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
                    "parallelism": "one workgroup per scenario"},
         "latency_ms": r["latency_ms"],
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r["achieved_GBs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "nr_kernel<double,256,16>",
+                     "frac": r["achieved_GBs"] / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic(f"nr_kernel_{cfg_name.lower()}_b{B}.txt", "fp64")
+                                 if cfg_name == "TX2000" else None),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": "nr_kernel<double, 256, 8>" if grid.n_bus == 2000 else "nr_kernel<double>",
                      "bytes_per_launch": r["algorithmic_bytes_per_launch"]},
         "fp64": runs["fp64"], "mixed": runs["mixed"],
         "mixed_vs_fp64": runs["mixed"]["value"] / r["value"],
@@ -307,6 +336,52 @@ def bench_serving(n_requests: int, lam: float) -> dict:
             "fp64": out["fp64"], "mixed": out["mixed"]}
 
 
+def counters_run(workload: str) -> dict:
+    """One launch per precision, plus a calibration copy, for hardware-counter runs.
+
+    Run under `rocprofv3 --pmc FETCH_SIZE` (then WRITE_SIZE) to measure HBM
+    traffic per launch; the calibration is one device-to-device copy of
+    512 MiB (read 512 MiB, write 512 MiB) whose counter values give the scale
+    of the counters.  Prints the algorithmic bytes of each launch.
+    """
+    import torch
+
+    from paper_2605_14103_amd import pf
+    n = 64 * 1024 * 1024
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    out = {"calibration_copy_bytes": 8 * n}
+    ctx = pf.Context(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    if workload == "feeder":
+        from workloads import feeder as fdm
+        fd = fdm.make_feeder(fdm.FEEDER300)
+        batch = fdm.make_batch(fd, fdm.FEEDER300)
+        net = pf.DistNetwork.from_feeder(ctx, fd)
+        sw, sd = dev(batch.s_wye), dev(batch.s_delta)
+        for prec in ("fp64", "mixed"):
+            res = net.solve(sw, sd, precision=pf.precision(prec))
+            torch.cuda.synchronize()
+            out[prec] = {"iters": res.iters.cpu().numpy().tolist()[:4]}
+    else:
+        from workloads import transmission as tx
+        cfg = {"tx2000": tx.TX2000, "tx30": tx.TX30}[workload]
+        grid = tx.make_grid(cfg)
+        batch = tx.make_batch(grid, cfg)
+        net = pf.TxNetwork.from_grid(ctx, grid)
+        p, q, vm = dev(batch.p_inj), dev(batch.q_inj), dev(batch.vm_set)
+        for prec in ("fp64", "mixed"):
+            res = net.solve(p, q, vm, precision=pf.precision(prec))
+            torch.cuda.synchronize()
+            out[prec] = {"algorithmic_bytes_per_launch": float(res.work_bytes.sum().item())}
+    net.close()
+    ctx.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,10 +392,15 @@ def main() -> int:
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--cpu-samples", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="one launch per precision plus a calibration copy, for rocprofv3 --pmc runs")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); run with --gpus 1", file=sys.stderr)
         return 2
+    if a.counters:
+        print(json.dumps(counters_run(a.workload)), flush=True)
+        return 0
     workers = min(16, os.cpu_count() or 1)
     cpu = None
     if not a.no_cpu and a.workload in ("tx2000", "tx30", "feeder"):
