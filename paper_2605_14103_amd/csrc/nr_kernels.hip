@@ -312,32 +312,37 @@ __device__ __forceinline__ Buf make_buf(const void* base) {
   return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, 0x7fffffff, 0x00020000)};
 }
 
-template <typename T>
-__device__ __forceinline__ T bld(const Buf& b, unsigned voff, unsigned soff);
-template <>
-__device__ __forceinline__ double bld<double>(const Buf& b, unsigned voff, unsigned soff) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0);
-  double d;
-  __builtin_memcpy(&d, &v, 8);
-  return d;
-}
-template <>
-__device__ __forceinline__ float bld<float>(const Buf& b, unsigned voff, unsigned soff) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0);
-  float f;
-  __builtin_memcpy(&f, &v, 4);
-  return f;
+// Cache policy bits of the per-scenario streams (workspace and Krylov basis);
+// 0 is the default policy.
+constexpr int WS_POLICY = 0;
+constexpr int BASIS_POLICY = 0;
+
+template <typename T, int CP = 0>
+__device__ __forceinline__ T bld(const Buf& b, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 8) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, CP);
+    T d;
+    __builtin_memcpy(&d, &v, 8);
+    return d;
+  } else {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, CP);
+    T f;
+    __builtin_memcpy(&f, &v, 4);
+    return f;
+  }
 }
 
+template <int CP = 0>
 __device__ __forceinline__ void bst(const Buf& b, double x, unsigned voff, unsigned soff) {
   decltype(__builtin_amdgcn_raw_buffer_load_b64(b.r, 0, 0, 0)) v;
   __builtin_memcpy(&v, &x, 8);
-  __builtin_amdgcn_raw_buffer_store_b64(v, b.r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(v, b.r, (int)voff, (int)soff, CP);
 }
+template <int CP = 0>
 __device__ __forceinline__ void bst(const Buf& b, float x, unsigned voff, unsigned soff) {
   decltype(__builtin_amdgcn_raw_buffer_load_b32(b.r, 0, 0, 0)) v;
   __builtin_memcpy(&v, &x, 4);
-  __builtin_amdgcn_raw_buffer_store_b32(v, b.r, (int)voff, (int)soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(v, b.r, (int)voff, (int)soff, CP);
 }
 
 // One scenario's FP64 workspace: 13 planes of NBP = KB BLOCK doubles.  Plane
@@ -350,10 +355,10 @@ struct Ws {
   Buf b;
   // plane a, bus slot k (k < 2 KB for the two-plane vectors F and DX)
   __device__ __forceinline__ double ld(int a, int k) const {
-    return bld<double>(b, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
+    return bld<double, WS_POLICY>(b, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
   }
   __device__ __forceinline__ void st(int a, int k, double v) const {
-    bst(b, v, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
+    bst<WS_POLICY>(b, v, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
   }
 };
 
@@ -363,10 +368,12 @@ struct Basis {
   static constexpr unsigned MP = 2u * KB * BLOCK;
   Buf b;
   __device__ __forceinline__ T ld(int i, int k) const {
-    return bld<T>(b, threadIdx.x * (unsigned)sizeof(T), ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+    return bld<T, BASIS_POLICY>(b, threadIdx.x * (unsigned)sizeof(T),
+                                ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
   }
   __device__ __forceinline__ void st(int i, int k, T v) const {
-    bst(b, v, threadIdx.x * (unsigned)sizeof(T), ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+    bst<BASIS_POLICY>(b, v, threadIdx.x * (unsigned)sizeof(T),
+                      ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
   }
 };
 
@@ -376,6 +383,26 @@ struct Basis {
 // remainder loop.  body(k, val, col) accumulates one entry of slot k; after a
 // slot's row, done(k) runs and its results are pinned so that later slots do
 // not keep this slot's operands alive.
+// One row (slice s, this lane) in rounds of four entries.
+template <typename V, typename Body>
+__device__ __forceinline__ void sell_row4(const Sell<V>& a, int s, Body&& body) {
+  const int lane = lane_id();
+  const int o = cld(a.off, (unsigned)s);
+  const int wd = cld(a.width, (unsigned)s);
+  for (int p = 0; p < wd; p += 4) {
+    V v[4];
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
+      v[u] = cld(a.val, q);
+      c[u] = cld(a.col, q);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) body(v[u], c[u]);
+  }
+}
+
 template <int KB, int NW, typename V, typename Body, typename Done>
 __device__ __forceinline__ void sell_slots(const Sell<V>& a, Body&& body, Done&& done) {
   const int wv = wave_id(), lane = lane_id();
@@ -537,38 +564,46 @@ __device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB
   constexpr int NW = BLOCK / WAVE;
   const unsigned nth = net.nth, npq = net.npq;
   T2* dv = reinterpret_cast<T2*>(lds);
-  // dV_i = V_i (j p_theta + p_|V| / |V|)
+  // dV_i = V_i (j p_theta + p_|V| / |V|).  The input w is dead after this
+  // loop, so the own buses' V stays in its registers for the second phase.
+  T vre[KB], vim[KB];
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     const unsigned i = row<BLOCK>(k);
     const T a = w[KB + k] * (T)ws.ld(IVM, k);
-    const T vr = (T)ws.ld(VRE, k), vi = (T)ws.ld(VIM, k);
+    vre[k] = (T)ws.ld(VRE, k);
+    vim[k] = (T)ws.ld(VIM, k);
     T2 d;
-    d.x = vr * a - vi * w[k];
-    d.y = vi * a + vr * w[k];
+    d.x = vre[k] * a - vim[k] * w[k];
+    d.y = vim[k] * a + vre[k] * w[k];
     dv[i] = d;
   }
   __syncthreads();
-  T dIr = 0, dIi = 0;
-  sell_slots<KB, NW>(
-      net.yT,
-      [&](int, T2 y, int c) {
-        const T2 d = dv[c];
-        dIr += y.x * d.x - y.y * d.y;
-        dIi += y.x * d.y + y.y * d.x;
-      },
-      [&](int k) {
-        const unsigned i = row<BLOCK>(k);
-        const T2 d = dv[i];
-        const T Ir = (T)ws.ld(IRE, k), Ii = (T)ws.ld(IIM, k);
-        const T vr = (T)ws.ld(VRE, k), vi = (T)ws.ld(VIM, k);
-        // dS = dV conj(I) + V conj(dI): real part on Theta, imaginary part on Q
-        w[k] = i < nth ? d.x * Ir + d.y * Ii + vr * dIr + vi * dIi : (T)0;
-        w[KB + k] = i < npq ? d.y * Ir - d.x * Ii + vi * dIr - vr * dIi : (T)0;
-        settle(w[k]);
-        settle(w[KB + k]);
-        dIr = dIi = 0;
-      });
+  // The own bus's I is fetched one slot ahead, so its HBM latency overlaps the
+  // previous slot's row.
+  const int wv = wave_id();
+  double nIr = ws.ld(IRE, 0), nIi = ws.ld(IIM, 0);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const T Ir = (T)nIr, Ii = (T)nIi, vr = vre[k], vi = vim[k];
+    if (k + 1 < KB) {
+      nIr = ws.ld(IRE, k + 1);
+      nIi = ws.ld(IIM, k + 1);
+    }
+    T dIr = 0, dIi = 0;
+    sell_row4(net.yT, k * NW + wv, [&](T2 y, int c) {
+      const T2 d = dv[c];
+      dIr += y.x * d.x - y.y * d.y;
+      dIi += y.x * d.y + y.y * d.x;
+    });
+    const unsigned i = row<BLOCK>(k);
+    const T2 d = dv[i];
+    // dS = dV conj(I) + V conj(dI): real part on Theta, imaginary part on Q
+    w[k] = i < nth ? d.x * Ir + d.y * Ii + vr * dIr + vi * dIi : (T)0;
+    w[KB + k] = i < npq ? d.y * Ir - d.x * Ii + vi * dIr - vr * dIi : (T)0;
+    settle(w[k]);
+    settle(w[KB + k]);
+  }
   __syncthreads();
 }
 
@@ -657,27 +692,33 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
     vs[i] = v;
   }
   __syncthreads();
-  double Ir = 0.0, Ii = 0.0, fmax = 0.0;
-  sell_slots<KB, NW>(
-      net.y64,
-      [&](int, double2 y, int c) {
-        const double2 v = vs[c];
-        Ir += y.x * v.x - y.y * v.y;
-        Ii += y.x * v.y + y.y * v.x;
-      },
-      [&](int k) {
-        const unsigned i = row<BLOCK>(k);
-        const double2 v = vs[i];
-        ws.st(IRE, k, Ir);
-        ws.st(IIM, k, Ii);
-        const double ft = i < nth ? v.x * Ir + v.y * Ii - ws.ld(PIN, k) : 0.0;
-        const double fv = i < npq ? v.y * Ir - v.x * Ii - ws.ld(QIN, k) : 0.0;
-        ws.st(FP, k, ft);
-        ws.st(FP, KB + k, fv);
-        fmax = nanmax(fmax, nanmax(fabs(ft), fabs(fv)));
-        settle(fmax);
-        Ir = Ii = 0.0;
-      });
+  const int wv = wave_id();
+  double fmax = 0.0;
+  double np = ws.ld(PIN, 0), nq = ws.ld(QIN, 0);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const double pk = np, qk = nq;
+    if (k + 1 < KB) {
+      np = ws.ld(PIN, k + 1);
+      nq = ws.ld(QIN, k + 1);
+    }
+    double Ir = 0.0, Ii = 0.0;
+    sell_row4(net.y64, k * NW + wv, [&](double2 y, int c) {
+      const double2 v = vs[c];
+      Ir += y.x * v.x - y.y * v.y;
+      Ii += y.x * v.y + y.y * v.x;
+    });
+    const unsigned i = row<BLOCK>(k);
+    const double2 v = vs[i];
+    ws.st(IRE, k, Ir);
+    ws.st(IIM, k, Ii);
+    const double ft = i < nth ? v.x * Ir + v.y * Ii - pk : 0.0;
+    const double fv = i < npq ? v.y * Ir - v.x * Ii - qk : 0.0;
+    ws.st(FP, k, ft);
+    ws.st(FP, KB + k, fv);
+    fmax = nanmax(fmax, nanmax(fabs(ft), fabs(fv)));
+    settle(fmax);
+  }
   return block_nanmax<BLOCK>(fmax, part);
 }
 
@@ -977,28 +1018,34 @@ __device__ void vjp(const TxDev<double>* netp, const Ws<BLOCK, KB>& ws, double (
     u[i] = t;
   }
   __syncthreads();
-  double gr = 0.0, gi = 0.0;  // (Y^T (c conj V))_i
-  sell_slots<KB, NW>(
-      net.yt,
-      [&](int, double2 y, int c) {
-        const double2 t = u[c];
-        gr += y.x * t.x - y.y * t.y;
-        gi += y.x * t.y + y.y * t.x;
-      },
-      [&](int k) {
-        const unsigned i = row<BLOCK>(k);
-        const double cr = w[k], ci = w[KB + k];
-        const double Ir = ws.ld(IRE, k), Ii = ws.ld(IIM, k);
-        const double hr = gr + cr * Ir - ci * Ii;  // + conj(c I)
-        const double hi = gi - (cr * Ii + ci * Ir);
-        const double vr = ws.ld(VRE, k), vi = ws.ld(VIM, k);
-        const double pr = hr * vr - hi * vi, pi = hr * vi + hi * vr;  // g V
-        w[k] = i < nth ? -pi : 0.0;
-        w[KB + k] = i < npq ? pr * ws.ld(IVM, k) : 0.0;
-        settle(w[k]);
-        settle(w[KB + k]);
-        gr = gi = 0.0;
-      });
+  const int wv = wave_id();
+  double nIr = ws.ld(IRE, 0), nIi = ws.ld(IIM, 0), nvr = ws.ld(VRE, 0), nvi = ws.ld(VIM, 0), niv = ws.ld(IVM, 0);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const double Ir = nIr, Ii = nIi, vr = nvr, vi = nvi, iv = niv;
+    if (k + 1 < KB) {
+      nIr = ws.ld(IRE, k + 1);
+      nIi = ws.ld(IIM, k + 1);
+      nvr = ws.ld(VRE, k + 1);
+      nvi = ws.ld(VIM, k + 1);
+      niv = ws.ld(IVM, k + 1);
+    }
+    double gr = 0.0, gi = 0.0;  // (Y^T (c conj V))_i
+    sell_row4(net.yt, k * NW + wv, [&](double2 y, int c) {
+      const double2 t = u[c];
+      gr += y.x * t.x - y.y * t.y;
+      gi += y.x * t.y + y.y * t.x;
+    });
+    const unsigned i = row<BLOCK>(k);
+    const double cr = w[k], ci = w[KB + k];
+    const double hr = gr + cr * Ir - ci * Ii;  // + conj(c I)
+    const double hi = gi - (cr * Ii + ci * Ir);
+    const double pr = hr * vr - hi * vi, pi = hr * vi + hi * vr;  // g V
+    w[k] = i < nth ? -pi : 0.0;
+    w[KB + k] = i < npq ? pr * iv : 0.0;
+    settle(w[k]);
+    settle(w[KB + k]);
+  }
   __syncthreads();
 }
 
