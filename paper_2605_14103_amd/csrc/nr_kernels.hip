@@ -227,7 +227,7 @@ __device__ __forceinline__ unsigned row(int k) {
 }
 
 struct NrLayout {
-  int xs, tmp, red, H, cs, sn, gres, gfin, y, total;
+  int xs, tmp, red, redn, H, cs, sn, gres, gfin, y, total;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
@@ -257,6 +257,7 @@ __host__ __device__ inline NrLayout nr_layout(int nbp, int nth, int npq, int kma
     L.tmp = o;
     o += align16(tmp_bytes);
   }
+  L.redn = o; o += align16(NW * 8);   // the norm reduction after the projection
   L.H = o;    o += align16(hcol(R) * ts);
   L.cs = o;   o += align16(R * ts);
   L.sn = o;   o += align16(R * ts);
@@ -274,6 +275,7 @@ struct Smem {
   T* tmp;
   T* red;
   double* redd;
+  T* redn;
   T* H;
   T* cs;
   T* sn;
@@ -290,6 +292,7 @@ __device__ Smem<T> carve(unsigned char* smem, const NrLayout& L) {
   s.tmp = reinterpret_cast<T*>(smem + L.tmp);
   s.red = reinterpret_cast<T*>(smem + L.red);
   s.redd = reinterpret_cast<double*>(smem + L.red);
+  s.redn = reinterpret_cast<T*>(smem + L.redn);
   s.H = reinterpret_cast<T*>(smem + L.H);
   s.cs = reinterpret_cast<T*>(smem + L.cs);
   s.sn = reinterpret_cast<T*>(smem + L.sn);
@@ -745,10 +748,9 @@ struct ByteModel {
 // a breakdown.  Returns the number of Arnoldi steps; *converged tells whether
 // the tolerance was met.
 //
-// Orthogonalisation runs on w = A v_j - v_j (see below).  One reduction gives
-// <v_i, w> and ||w||^2 together, and ||w'||^2 = ||w||^2 - sum h_i^2 after the
-// projection; a second classical Gram-Schmidt pass runs when that leaves less
-// than 1/64 of the norm.  Every thread applies the Givens
+// Orthogonalisation: one reduction gives <v_i, w> and ||w||^2 together, a
+// second one ||w'||^2 after the projection; a second classical Gram-Schmidt
+// pass runs when the projection leaves less than 1/64 of the norm.  Every thread applies the Givens
 // rotations to the new Hessenberg column itself (same data, same operations),
 // so no barrier is needed after them; thread 0 alone stores H, the rotations
 // and the rotated right-hand side for later steps.
@@ -805,19 +807,19 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
     for (int j = 0; j < R; ++j) {
       apply_a(w);
       apply_m(w);
-      // Arnoldi on A - I: the same Krylov space (H = H' + I), and with a good
-      // preconditioner A v_j is close to v_j, so the shifted vector loses far
-      // less to the projection than A v_j itself would.
-#pragma unroll
-      for (int k = 0; k < K; ++k) w[k] -= basis.ld(j, k);
       T ss0 = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) ss0 += w[k] * w[k];
       T* p1 = next_part();
       multi_dot<T, BLOCK, KB>(basis, j + 1, w, ss0, p1);
-      const T hh1 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
+      subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
       const T wn2 = part_sum<T, NW>(p1, j + 1);
-      T nrm2 = wn2 - hh1;
+      // ||w'||^2 by its own reduction (with a good preconditioner most of w
+      // lies in the span of the basis, so ||w||^2 - sum h_i^2 would cancel)
+      T s1 = 0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) s1 += w[k] * w[k];
+      T nrm2 = block_sum<T, BLOCK>(s1, s.redn);
       // Second pass only when the projection removed all but 1/64 of the
       // norm: the first pass's rounding then leaves the new vector orthogonal
       // to about 64 ulp, far below the GMRES tolerance, and a pass is saved in
@@ -825,22 +827,18 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
       const bool again = nrm2 < (T)(1.0 / 4096.0) * wn2;
       T* p2 = p1;
       if (again) {
-        T s1 = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) s1 += w[k] * w[k];
         p2 = next_part();
         multi_dot<T, BLOCK, KB>(basis, j + 1, w, s1, p2);
         const T hh2 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p2);
-        nrm2 = part_sum<T, NW>(p2, j + 1) - hh2;
+        nrm2 = nrm2 - hh2;   // the second pass removes only a small remainder
       }
       *work += bm.jvp() + bm.pre() + (again ? 2 : 1) * bm.orth_pass(j);
       const T hn = sqrt(nrm2 > (T)0 ? nrm2 : (T)0);
       // Hessenberg column j: h_i (+ second-pass h_i), rotated by the previous Givens rotations
       T* Hj = s.H + hcol(j);
-      T cur = part_sum<T, NW>(p1, 0) + (again ? part_sum<T, NW>(p2, 0) : (T)0) + (j == 0 ? (T)1 : (T)0);
+      T cur = part_sum<T, NW>(p1, 0) + (again ? part_sum<T, NW>(p2, 0) : (T)0);
       for (int i = 0; i < j; ++i) {
-        const T nxt = part_sum<T, NW>(p1, i + 1) + (again ? part_sum<T, NW>(p2, i + 1) : (T)0) +
-                      (i + 1 == j ? (T)1 : (T)0);
+        const T nxt = part_sum<T, NW>(p1, i + 1) + (again ? part_sum<T, NW>(p2, i + 1) : (T)0);
         const T c = s.cs[i], sn = s.sn[i];
         const T a = c * cur + sn * nxt;
         cur = -sn * cur + c * nxt;
