@@ -16,30 +16,9 @@
 
 #include "common.hpp"
 #include "factor.hpp"
+#include "sell.hpp"
 
 namespace pfx {
-
-// Sliced ELLPACK: rows are grouped in slices of 64 (one wavefront), each
-// slice padded to its longest row.  Entry p of the row on lane l of slice s
-// sits at off[s] + 64 p + l; padding entries have column 0 and value 0.
-template <typename V>
-struct Sell {
-  const int* off;     // [n_slices]
-  const int* width;   // [n_slices]
-  const int* col;
-  const V* val;
-};
-
-template <typename T>
-struct Vec2;
-template <>
-struct Vec2<double> {
-  using type = double2;
-};
-template <>
-struct Vec2<float> {
-  using type = float2;
-};
 
 // Device view of one explicit factor (factor.hpp, ExplicitFactor) laid out for
 // one workgroup of `block` threads.
@@ -79,15 +58,6 @@ struct TxDev {
   const double* br_ys_re;
   const double* br_ys_im;
   const double* br_b;
-};
-
-// Host-built sliced ELLPACK with device copies of its values in FP64 and FP32.
-struct SellBuffers {
-  int n_slices = 0;
-  long entries = 0;
-  DeviceBuffer off, width, col, val64, val32;
-  template <typename V>
-  Sell<V> view() const;
 };
 
 struct EfBuffers {

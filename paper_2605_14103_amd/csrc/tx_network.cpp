@@ -17,72 +17,7 @@ namespace {
 
 constexpr int SLICE = 64;
 
-using Entry = std::tuple<int, double, double>;   // column, value (re), value (im)
-using Row = std::vector<Entry>;
-
-struct SellHost {
-  std::vector<int> off, width, col;
-  std::vector<double> re, im;
-  long entries = 0;
-};
-
-// Rows (a multiple of 64 of them) into slices of 64 consecutive rows.  Each
-// slice's width is at least 1 and a multiple of `quantum` (padding entries are
-// zeros), so that kernels may read a slice's last entry unconditionally and
-// unroll by the quantum without a remainder.
-SellHost build_sell(const std::vector<Row>& rows, int quantum = 1) {
-  SellHost h;
-  const int ns = (int)rows.size() / SLICE;
-  h.off.resize(ns);
-  h.width.resize(ns);
-  int cur = 0;
-  for (int s = 0; s < ns; ++s) {
-    int w = 1;
-    for (int l = 0; l < SLICE; ++l) w = std::max(w, (int)rows[s * SLICE + l].size());
-    w = (w + quantum - 1) / quantum * quantum;
-    h.off[s] = cur;
-    h.width[s] = w;
-    cur += SLICE * w;
-  }
-  h.col.assign(cur, 0);
-  h.re.assign(cur, 0.0);
-  h.im.assign(cur, 0.0);
-  for (int s = 0; s < ns; ++s)
-    for (int l = 0; l < SLICE; ++l) {
-      const Row& r = rows[s * SLICE + l];
-      for (size_t p = 0; p < r.size(); ++p) {
-        const int q = h.off[s] + (int)p * SLICE + l;
-        h.col[q] = std::get<0>(r[p]);
-        h.re[q] = std::get<1>(r[p]);
-        h.im[q] = std::get<2>(r[p]);
-      }
-      h.entries += (long)r.size();
-    }
-  return h;
-}
-
-void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b) {
-  b.n_slices = (int)h.off.size();
-  b.entries = h.entries;
-  b.off = upload(ctx, h.off);
-  b.width = upload(ctx, h.width);
-  b.col = upload(ctx, h.col);
-  if (cplx) {
-    std::vector<double> v64(2 * h.re.size());
-    std::vector<float> v32(2 * h.re.size());
-    for (size_t i = 0; i < h.re.size(); ++i) {
-      v64[2 * i] = h.re[i];
-      v64[2 * i + 1] = h.im[i];
-      v32[2 * i] = (float)h.re[i];
-      v32[2 * i + 1] = (float)h.im[i];
-    }
-    b.val64 = upload(ctx, v64);
-    b.val32 = upload(ctx, v32);
-  } else {
-    b.val64 = upload(ctx, h.re);
-    b.val32 = upload(ctx, std::vector<float>(h.re.begin(), h.re.end()));
-  }
-}
+using Row = SellRow;
 
 // Lay out one explicit factor for workgroups of `block` threads with kb bus
 // slots each (the factor order has N <= kb * block rows).
@@ -202,23 +137,6 @@ void check_factor(const SparseSym& A, const ExplicitFactor& F, const char* name)
 }
 
 }  // namespace
-
-template <>
-Sell<double> SellBuffers::view<double>() const {
-  return Sell<double>{off.as<int>(), width.as<int>(), col.as<int>(), val64.as<double>()};
-}
-template <>
-Sell<float> SellBuffers::view<float>() const {
-  return Sell<float>{off.as<int>(), width.as<int>(), col.as<int>(), val32.as<float>()};
-}
-template <>
-Sell<double2> SellBuffers::view<double2>() const {
-  return Sell<double2>{off.as<int>(), width.as<int>(), col.as<int>(), val64.as<double2>()};
-}
-template <>
-Sell<float2> SellBuffers::view<float2>() const {
-  return Sell<float2>{off.as<int>(), width.as<int>(), col.as<int>(), val32.as<float2>()};
-}
 
 template <typename T>
 EfDev<T> EfBuffers::view() const {
