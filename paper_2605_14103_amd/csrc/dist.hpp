@@ -15,21 +15,22 @@
 #include <vector>
 
 #include "common.hpp"
+#include "sell.hpp"
 
 namespace pfx {
 
+// Free nodes are also grouped in slices of 64 (one wavefront) for the
+// residual kernel: nNs = nN rounded up to 64, and a thread of the residual's
+// workgroup owns nodes t + k * ZB_THREADS.
 struct DistDev {
-  int nN, Kp, Np;
-  const int* y_ptr;        // Y_NN CSR over free nodes
-  const int* y_col;
-  const double* y_re;
-  const double* y_im;
-  const double* c;         // Y_NS v_S, complex interleaved [nN]
+  int nN, nNs, Kp, Np;
+  Sell<double2> y;         // Y_NN over free nodes (nNs rows, widths multiples of 4)
+  const int4* node;        // [nNs] x: caller's index | (wye load ? 1 << 30 : 0),
+                           //       y: next phase of a delta bus (-1 if none),
+                           //       z: previous phase, w: caller's index of z
+  const double2* c;        // [nNs] Y_NS v_S (zero past nN)
   const double* v0;        // no-load voltage, complex interleaved [nN]
   const int* free2ext;     // free node -> caller's node index
-  const uint8_t* wye;      // [nN] 1 if the node may carry a wye load
-  const int* d_next;       // [nN] delta partner: next phase of the bus (-1 if not delta)
-  const int* d_prev;       // [nN] previous phase of the bus
 };
 
 struct DistNetwork {
@@ -38,7 +39,8 @@ struct DistNetwork {
   int slack[3] = {0, 1, 2};
   double v_slack[6] = {0, 0, 0, 0, 0, 0};
   std::vector<int> free2ext;
-  DeviceBuffer y_ptr, y_col, y_re, y_im, c, v0, free2ext_d, wye, d_next, d_prev;
+  SellBuffers y;
+  DeviceBuffer node, c, v0, free2ext_d;
   DeviceBuffer W64, W32;   // Kp x Np real-block Z (Np = 2 nN rounded up to the N tile)
   DeviceBuffer slack_d;    // 3 slack node indices
   DeviceBuffer vslack_d;   // 6 doubles
@@ -56,7 +58,10 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
                                  const int32_t* wye_node, int n_delta, const int32_t* delta_nodes,
                                  const pf_opts& setup);
 
-// GEMM tile sizes shared by the host sizing and the kernels.
+// Residual workgroup size and GEMM tile sizes shared by the host sizing and
+// the kernels.
+constexpr int ZB_THREADS = 256;
+constexpr int ZB_MAX_FREE = 4096;   // free nodes (the residual keeps v in LDS)
 constexpr int ZB_BM = 128;   // scenarios per tile
 constexpr int ZB_BN = 128;   // output reals per tile
 constexpr int ZB_BK = 16;    // K step

@@ -75,18 +75,14 @@ int round_up(int x, int m) { return (x + m - 1) / m * m; }
 DistDev DistNetwork::view() const {
   DistDev d;
   d.nN = nN;
+  d.nNs = round_up(nN, 64);
   d.Kp = Kp;
   d.Np = Np;
-  d.y_ptr = y_ptr.as<int>();
-  d.y_col = y_col.as<int>();
-  d.y_re = y_re.as<double>();
-  d.y_im = y_im.as<double>();
-  d.c = c.as<double>();
+  d.y = y.view<double2>();
+  d.node = node.as<int4>();
+  d.c = c.as<double2>();
   d.v0 = v0.as<double>();
   d.free2ext = free2ext_d.as<int>();
-  d.wye = wye.as<uint8_t>();
-  d.d_next = d_next.as<int>();
-  d.d_prev = d_prev.as<int>();
   return d;
 }
 
@@ -121,13 +117,17 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
       net->free2ext.push_back(i);
     }
   const int nN = (int)net->free2ext.size();
+  require(nN <= ZB_MAX_FREE, "at most " + std::to_string(ZB_MAX_FREE) + " free nodes are supported");
+  require(n_node < (1 << 30), "too many nodes");
   net->nN = nN;
+  const int nNs = round_up(nN, 64);
   net->Kp = round_up(2 * nN, ZB_BK);
   net->Np = round_up(2 * nN, ZB_BN);
 
-  // Y_NN (CSR over free nodes) and c = Y_NS v_S.
-  std::vector<int> yp(nN + 1, 0), yc;
-  std::vector<double> yr, yi, cc(2 * (size_t)nN, 0.0);
+  // Y_NN (rows over free nodes) and c = Y_NS v_S.
+  std::vector<SellRow> rows(nNs);
+  std::vector<double> cc(2 * (size_t)nNs, 0.0);
+  int nnz_nn = 0;
   std::vector<cplx> Yd((size_t)nN * nN, cplx(0.0));
   for (int fi = 0; fi < nN; ++fi) {
     const int e = net->free2ext[fi];
@@ -146,16 +146,14 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
       }
     }
     for (auto& [j, y] : row) {
-      yc.push_back(j);
-      yr.push_back(y.real());
-      yi.push_back(y.imag());
+      rows[fi].emplace_back(j, y.real(), y.imag());
       Yd[(size_t)fi * nN + j] = y;
     }
-    yp[fi + 1] = (int)yc.size();
+    nnz_nn += (int)row.size();
     cc[2 * fi] = acc.real();
     cc[2 * fi + 1] = acc.imag();
   }
-  net->nnz = (int)yc.size();
+  net->nnz = nnz_nn;
 
   invert_dense(Yd, nN);  // Yd now holds Z
   std::vector<double> v0(2 * (size_t)nN);
@@ -201,16 +199,20 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
   net->n_wye = n_wye;
   net->n_delta = n_delta;
 
-  net->y_ptr = upload(ctx, yp);
-  net->y_col = upload(ctx, yc);
-  net->y_re = upload(ctx, yr);
-  net->y_im = upload(ctx, yi);
+  std::vector<int> nodes(4 * (size_t)nNs, 0);
+  for (int i = 0; i < nN; ++i) {
+    nodes[4 * i] = net->free2ext[i] | (wye[i] ? 1 << 30 : 0);
+    nodes[4 * i + 1] = dn[i];
+    nodes[4 * i + 2] = dpv[i];
+    nodes[4 * i + 3] = dpv[i] >= 0 ? net->free2ext[dpv[i]] : 0;
+  }
+  for (int i = nN; i < nNs; ++i) nodes[4 * i + 1] = -1;
+
+  upload_sell(ctx, build_sell(rows, 4), true, net->y);
+  net->node = upload(ctx, nodes);
   net->c = upload(ctx, cc);
   net->v0 = upload(ctx, v0);
   net->free2ext_d = upload(ctx, net->free2ext);
-  net->wye = upload(ctx, wye);
-  net->d_next = upload(ctx, dn);
-  net->d_prev = upload(ctx, dpv);
   net->W64 = upload(ctx, W);
   net->W32 = upload(ctx, std::vector<float>(W.begin(), W.end()));
   net->slack_d = upload(ctx, std::vector<int>(net->slack, net->slack + 3));

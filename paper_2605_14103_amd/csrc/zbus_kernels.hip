@@ -10,7 +10,8 @@
 //
 // Kernels per iteration:
 //   zb_residual   one workgroup per scenario: wye and delta load currents,
-//                 sparse Y_NN v, r, max |v * conj(r)|, flags, sum |v|
+//                 sparse Y_NN v (sliced ELLPACK, v staged in LDS), r,
+//                 max |v * conj(r)|, flags, sum |v|
 //   zb_gemm       D = R W (real-block form of Z r) on MFMA 16x16x4 tiles, with
 //                 the FP64 update v += D fused into the epilogue
 #include <hip/hip_runtime.h>
@@ -18,54 +19,41 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <type_traits>
 
+#include "device_ops.hpp"
 #include "dist.hpp"
 
 namespace pfx {
 
 namespace {
 
-constexpr int WAVE = 64;
-constexpr int ZB_THREADS = 256;
+// Complex values of per-scenario rows: one 16-byte load or an 8/16-byte store.
+typedef double D2 __attribute__((ext_vector_type(2)));
+typedef float F2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ double nanmax(double a, double b) {
-  if (a != a) return a;
-  if (b != b) return b;
-  return a > b ? a : b;
+__device__ __forceinline__ D2 ld2(const double* base, unsigned i) {
+  typedef __attribute__((address_space(1))) const D2 GD2;
+  return ((GD2*)base)[i];
 }
 
-template <int BLOCK>
-__device__ double block_nanmax(double v, double* red) {
-  for (int off = WAVE / 2; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, WAVE));
-  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
-  __syncthreads();
-  double s = red[0];
-  for (int i = 1; i < BLOCK / WAVE; ++i) s = nanmax(s, red[i]);
-  __syncthreads();
-  return s;
+__device__ __forceinline__ void st2(double* base, unsigned i, double x, double y) {
+  typedef __attribute__((address_space(1))) D2 GD2;
+  ((GD2*)base)[i] = D2{x, y};
 }
 
-template <int BLOCK>
-__device__ double block_sum(double v, double* red) {
-  for (int off = WAVE / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
-  if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < BLOCK / WAVE; ++i) s += red[i];
-  __syncthreads();
-  return s;
+__device__ __forceinline__ void st2(float* base, unsigned i, double x, double y) {
+  typedef __attribute__((address_space(1))) F2 GF2;
+  ((GF2*)base)[i] = F2{(float)x, (float)y};
 }
 
-// conj(s / v) for complex s, v given as (re, im)
-__device__ __forceinline__ void conj_div(double sr, double si, double vr, double vi, double& outr,
-                                         double& outi) {
+// conj(s / v) for complex s, v
+__device__ __forceinline__ D2 conj_div(D2 s, double vr, double vi) {
   const double d = vr * vr + vi * vi;
-  // s / v = s conj(v) / |v|^2
-  const double qr = (sr * vr + si * vi) / d;
-  const double qi = (si * vr - sr * vi) / d;
-  outr = qr;
-  outi = -qi;
+  return D2{(s.x * vr + s.y * vi) / d, -(s.y * vr - s.x * vi) / d};
 }
+
+constexpr int WYE_BIT = 1 << 30;
 
 __global__ __launch_bounds__(ZB_THREADS) void zb_init(DistDev net, ZbusLaunch a) {
   const int b = blockIdx.x;
@@ -81,59 +69,103 @@ __global__ __launch_bounds__(ZB_THREADS) void zb_init(DistDev net, ZbusLaunch a)
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(ZB_THREADS) void zb_residual(DistDev net, ZbusLaunch a, int it) {
-  extern __shared__ double vs[];  // [2 nN]
-  __shared__ double red[ZB_THREADS / WAVE];
+// One workgroup per scenario; wave w owns node slices k * 4 + w (k < KB).
+// Per node: the load current i(v) (wye: -conj(S / v); delta: the two branch
+// currents of the node's delta), the row of Y_NN v + c from the sliced
+// ELLPACK copy of Y_NN (entries read in rounds of 4), the residual r (stored
+// in the GEMM's type), |v conj(r)| and |v|.  The workgroup's max and sum are
+// finished by thread 0, which also sets the scenario's flags.
+template <typename T, int KB>
+__global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8))) void zb_residual(
+    DistDev net, ZbusLaunch a, int it) {
+  constexpr int NW = ZB_THREADS / WAVE;
+  extern __shared__ D2 vs[];  // [nNs]
+  __shared__ double red[2][NW];
   const int b = blockIdx.x;
   if (a.active[b] == 0) return;
-  const int nN = net.nN;
-  const double* v = a.v + (int64_t)b * net.Kp;
-  for (int i = threadIdx.x; i < 2 * nN; i += ZB_THREADS) vs[i] = v[i];
+  const int nN = net.nN, nNs = net.nNs;
+  const double* vrow = a.v + (int64_t)b * net.Kp;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const unsigned i = threadIdx.x + k * ZB_THREADS;
+    if (i < (unsigned)nNs) vs[i] = i < (unsigned)nN ? ld2(vrow, i) : D2{0.0, 0.0};
+  }
   __syncthreads();
   const double* SW = a.s_wye + 2 * (int64_t)b * a.ld;
   const double* SD = a.s_delta + 2 * (int64_t)b * a.ld;
   T* r = reinterpret_cast<T*>(a.r) + (int64_t)b * net.Kp;
+  const int wv = wave_id(), lane = lane_id();
   double mm = 0.0, sabs = 0.0;
-  for (int i = threadIdx.x; i < nN; i += ZB_THREADS) {
-    const double vr = vs[2 * i], vi = vs[2 * i + 1];
-    double ir = 0.0, ii = 0.0;
-    if (net.wye[i]) {  // wye: -conj(S / v)
-      const int e = net.free2ext[i];
-      double cr, ci;
-      conj_div(SW[2 * e], SW[2 * e + 1], vr, vi, cr, ci);
-      ir -= cr;
-      ii -= ci;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const int sl = k * NW + wv;
+    if (sl * WAVE >= nNs) break;
+    const unsigned i = (unsigned)(sl * WAVE + lane);
+    const int4 nd = cld(net.node, i);
+    const double2 c = cld(net.c, i);
+    const int e = nd.x & (WYE_BIT - 1);
+    D2 sw = {0.0, 0.0}, sx = {0.0, 0.0}, sp = {0.0, 0.0};
+    if (nd.x & WYE_BIT) sw = ld2(SW, (unsigned)e);
+    if (nd.y >= 0) {
+      sx = ld2(SD, (unsigned)e);
+      sp = ld2(SD, (unsigned)nd.w);
     }
-    const int nx = net.d_next[i];
-    if (nx >= 0) {  // delta: branch x->next carries S_x, branch prev->x carries S_prev
-      const int pv = net.d_prev[i];
-      const int e = net.free2ext[i], ep = net.free2ext[pv];
-      double axr, axi, apr, api;
-      conj_div(SD[2 * e], SD[2 * e + 1], vr - vs[2 * nx], vi - vs[2 * nx + 1], axr, axi);
-      conj_div(SD[2 * ep], SD[2 * ep + 1], vs[2 * pv] - vr, vs[2 * pv + 1] - vi, apr, api);
-      ir -= axr - apr;
-      ii -= axi - api;
+    double yr = c.x, yi = c.y;
+    const int o = cld(net.y.off, (unsigned)sl);
+    const int wd = cld(net.y.width, (unsigned)sl);
+    for (int p = 0; p < wd; p += 4) {
+      double2 g[4];
+      int cj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
+        g[u] = cld(net.y.val, q);
+        cj[u] = cld(net.y.col, q);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const D2 x = vs[cj[u]];
+        yr += g[u].x * x.x - g[u].y * x.y;
+        yi += g[u].x * x.y + g[u].y * x.x;
+      }
     }
-    double yr = net.c[2 * i], yi = net.c[2 * i + 1];
-    for (int p = net.y_ptr[i]; p < net.y_ptr[i + 1]; ++p) {
-      const int j = net.y_col[p];
-      const double gr = net.y_re[p], gi = net.y_im[p];
-      const double xr = vs[2 * j], xi = vs[2 * j + 1];
-      yr += gr * xr - gi * xi;
-      yi += gr * xi + gi * xr;
+    if (i < (unsigned)nN) {
+      const D2 v = vs[i];
+      double ir = 0.0, ii = 0.0;
+      if (nd.x & WYE_BIT) {
+        const D2 q = conj_div(sw, v.x, v.y);
+        ir -= q.x;
+        ii -= q.y;
+      }
+      if (nd.y >= 0) {  // branch x->next carries S_x, branch prev->x carries S_prev
+        const D2 vn = vs[nd.y], vp = vs[nd.z];
+        const D2 ax = conj_div(sx, v.x - vn.x, v.y - vn.y);
+        const D2 ap = conj_div(sp, vp.x - v.x, vp.y - v.y);
+        ir -= ax.x - ap.x;
+        ii -= ax.y - ap.y;
+      }
+      const double rr = ir - yr, ri = ii - yi;
+      const double dr = v.x * rr + v.y * ri, di = v.y * rr - v.x * ri;  // v conj(r)
+      mm = nanmax(mm, sqrt(dr * dr + di * di));
+      sabs += sqrt(v.x * v.x + v.y * v.y);
+      st2(r, i, rr, ri);
     }
-    const double rr = ir - yr, ri = ii - yi;
-    // v * conj(r)
-    const double dr = vr * rr + vi * ri, di = vi * rr - vr * ri;
-    mm = nanmax(mm, sqrt(dr * dr + di * di));
-    sabs += sqrt(vr * vr + vi * vi);
-    r[2 * i] = (T)rr;
-    r[2 * i + 1] = (T)ri;
   }
-  mm = block_nanmax<ZB_THREADS>(mm, red);
-  sabs = block_sum<ZB_THREADS>(sabs, red);
+  mm = wave_nanmax(mm);
+  sabs = wave_total(sabs);
+  if (lane == 0) {
+    red[0][wv] = mm;
+    red[1][wv] = sabs;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
+    mm = red[0][0];
+    sabs = red[1][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      mm = nanmax(mm, red[0][w]);
+      sabs += red[1][w];
+    }
     double* st = a.st + 3 * (int64_t)b;
     st[0] = mm;
     if (it > 0) st[2] = fabs(sabs - st[1]);
@@ -178,11 +210,20 @@ struct Mfma<float> {
 // D = R W on a ZB_BM x ZB_BN tile per workgroup (4 waves, 2 x 2, 64 x 64 each,
 // 4 x 4 MFMA 16x16x4 tiles per wave), K in steps of ZB_BK staged through LDS,
 // double buffered.  Epilogue: v += D for active scenarios (FP64).
+//
+// LDS rows are padded by 16 elements so that the four row groups a fragment
+// read touches (one per 16 lanes) start in different banks.  Two workgroups
+// per CU (two waves per SIMD) keep the matrix pipe busy while the other wave
+// waits on LDS or memory: the 64 accumulators per lane live in AGPRs and the
+// staging registers must fit beside them.
+constexpr int ZB_PAD = 16;
+
 template <typename T>
-__global__ __launch_bounds__(256) void zb_gemm(DistDev net, const T* __restrict__ W, ZbusLaunch a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zb_gemm(
+    DistDev net, const T* __restrict__ W, ZbusLaunch a) {
   using V4 = typename Mfma<T>::V4;
-  __shared__ T As[2][ZB_BK][ZB_BM];
-  __shared__ T Bs[2][ZB_BK][ZB_BN];
+  __shared__ T As[2][ZB_BK][ZB_BM + ZB_PAD];
+  __shared__ T Bs[2][ZB_BK][ZB_BN + ZB_PAD];
   const int tile_n = blockIdx.x, tile_m = blockIdx.y;
   const int row0 = tile_m * ZB_BM, col0 = tile_n * ZB_BN;
   const int t = threadIdx.x;
@@ -207,26 +248,23 @@ __global__ __launch_bounds__(256) void zb_gemm(DistDev net, const T* __restrict_
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
 
-  T ra[8], rb[8];
-  auto gload = [&](int kt) {
+  // Global tiles are prefetched two K steps ahead into two register sets
+  // (tile j goes through set j & 1), LDS is double buffered (tile j in
+  // buffer j & 1): a tile's loads have a whole K step of MFMAs to land.
+  T ra[2][8], rb[2][8];
+  auto gload = [&](int kt, int set) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) ra[q] = Ag[kt * ZB_BK + q];
+    for (int q = 0; q < 8; ++q) ra[set][q] = Ag[kt * ZB_BK + q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) rb[q] = Bg[(int64_t)kt * ZB_BK * Np + q];
+    for (int q = 0; q < 8; ++q) rb[set][q] = Bg[(int64_t)kt * ZB_BK * Np + q];
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int set) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[buf][ac + q][ar] = ra[q];
+    for (int q = 0; q < 8; ++q) As[buf][ac + q][ar] = ra[set][q];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) Bs[buf][br][bc + q] = rb[q];
+    for (int q = 0; q < 8; ++q) Bs[buf][br][bc + q] = rb[set][q];
   };
-  const int nk = Kp / ZB_BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload(kt + 1);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < ZB_BK / 4; ++kk) {
       const int kr = kk * 4 + lane / 16;
@@ -240,8 +278,23 @@ __global__ __launch_bounds__(256) void zb_gemm(DistDev net, const T* __restrict_
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(af[i], bf[j], acc[i][j]);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
+  };
+  const int nk = Kp / ZB_BK;
+  // one K step on tile kt (in LDS buffer and register set P = kt & 1)
+  auto step = [&](int kt, auto par) {
+    constexpr int P = decltype(par)::value;
+    if (kt + 2 < nk) gload(kt + 2, P);
+    compute(P);
+    if (kt + 1 < nk) sstore(P ^ 1, P ^ 1);
     __syncthreads();
+  };
+  gload(0, 0);
+  sstore(0, 0);
+  if (nk > 1) gload(1, 1);
+  __syncthreads();
+  for (int kt = 0; kt < nk; kt += 2) {
+    step(kt, std::integral_constant<int, 0>{});
+    if (kt + 1 < nk) step(kt + 1, std::integral_constant<int, 1>{});
   }
   const int ncol = 2 * net.nN;
 #pragma unroll
@@ -288,7 +341,13 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
   const int B = a.batch;
   const int mt = (B + ZB_BM - 1) / ZB_BM;
   const int nt = net.Np / ZB_BN;
-  const size_t lds = 2 * (size_t)net.nN * sizeof(double);
+  const size_t lds = (size_t)d.nNs * 2 * sizeof(double);
+  const int kb_need = (d.nNs + ZB_THREADS - 1) / ZB_THREADS;
+  auto residual = kb_need <= 1 ? zb_residual<T, 1>
+                  : kb_need <= 2 ? zb_residual<T, 2>
+                  : kb_need <= 4 ? zb_residual<T, 4>
+                  : kb_need <= 8 ? zb_residual<T, 8>
+                                 : zb_residual<T, 16>;
   hipLaunchKernelGGL(zb_init, dim3(B), dim3(ZB_THREADS), 0, s, d, a);
   PFX_HIP(hipGetLastError());
   PFX_HIP(hipMemsetAsync(a.count, 0, sizeof(int32_t) * (a.max_iter + 1), s));
@@ -297,7 +356,7 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
   PFX_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   try {
     for (int it = 0; it <= a.max_iter; ++it) {
-      hipLaunchKernelGGL(zb_residual<T>, dim3(B), dim3(ZB_THREADS), lds, s, d, a, it);
+      hipLaunchKernelGGL(residual, dim3(B), dim3(ZB_THREADS), lds, s, d, a, it);
       PFX_HIP(hipGetLastError());
       PFX_HIP(hipMemcpyAsync(a.count_host + it, a.count + it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
       PFX_HIP(hipEventRecord(ev[it & 1], s));
