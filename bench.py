@@ -112,14 +112,28 @@ def time_steps(fn, steps: int, warmup: int):
     return ms, wall, out
 
 
-TRAFFIC_SOURCES = ("paper_2605_14103_amd/csrc/nr_kernels.hip", "paper_2605_14103_amd/csrc/tx_network.cpp",
-                   "paper_2605_14103_amd/csrc/factor.cpp")
+_CSRC = "paper_2605_14103_amd/csrc/"
+# Sources whose change invalidates a committed counter summary, per kernel family.
+TRAFFIC_SOURCES = {
+    "nr": tuple(_CSRC + f for f in ("nr_kernels.hip", "device_ops.hpp", "tx.hpp", "tx_network.cpp", "factor.cpp",
+                                    "sell.hpp", "sell.cpp")),
+    "zbus": tuple(_CSRC + f for f in ("zbus_kernels.hip", "device_ops.hpp", "dist.hpp", "dist_network.cpp",
+                                      "sell.hpp", "sell.cpp")),
+}
 
 
-def measured_traffic(profile: str, key: str) -> float | None:
+def source_digest(family: str) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[family]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(profile: str, key: str, family: str = "nr") -> float | None:
     """HBM bytes per launch from a committed counter summary, or None when the
     kernel sources have changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
@@ -127,13 +141,7 @@ def measured_traffic(profile: str, key: str) -> float | None:
     for line in open(path):
         if line.startswith("TRAFFIC_JSON "):
             rec = json.loads(line[len("TRAFFIC_JSON "):])
-    if rec is None:
-        return None
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != rec.get("source_sha256_16"):
+    if rec is None or source_digest(family) != rec.get("source_sha256_16"):
         return None
     return rec.get(key)
 
@@ -231,11 +239,21 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
                       "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99))},
                       "useful_gemm_TFLOPs": gemm_flops / (mean_ms * 1e-3) / 1e12}
     r = runs["fp64"]
+    tf = r["useful_gemm_TFLOPs"]
     line = {"metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"feeder300: Z-bus, {fd.n_node} phase nodes, batch {B}", "global_batch": B},
-            "latency_ms": r["latency_ms"], "fp64": runs["fp64"], "mixed": runs["mixed"],
+            "latency_ms": r["latency_ms"],
+            "roofline": {"bound": "mfma", "achieved": tf, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tf / FP64_MFMA_TFLOPS,
+                         "traffic": measured_traffic("zbus_feeder300_b4096.txt", "gemm_fp64", "zbus"),
+                         "traffic_unit": "HBM bytes per full zb_gemm<double> launch (rocprofv3 FETCH_SIZE + "
+                                         "WRITE_SIZE, copy-calibrated)",
+                         "kernel": "zb_gemm<double>",
+                         "basis": "useful complex flops (8 nN^2 per scenario and iteration) over the whole "
+                                  "solve time, residual kernels and launch gaps included"},
+            "fp64": runs["fp64"], "mixed": runs["mixed"],
             "mixed_vs_fp64": runs["mixed"]["value"] / r["value"]}
     if cpu is not None:
         line["cpu_baseline"] = cpu

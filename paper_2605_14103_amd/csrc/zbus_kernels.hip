@@ -214,17 +214,25 @@ struct Mfma<float> {
 // LDS rows are padded by 16 elements so that the four row groups a fragment
 // read touches (one per 16 lanes) start in different banks.  Two workgroups
 // per CU (two waves per SIMD) keep the matrix pipe busy while the other wave
-// waits on LDS or memory: the 64 accumulators per lane live in AGPRs and the
-// staging registers must fit beside them.
+// waits on LDS or memory: the 4 x 4 accumulator tiles (64 values per lane)
+// and the two staging register sets must fit in half the register file.
 constexpr int ZB_PAD = 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zb_gemm(
     DistDev net, const T* __restrict__ W, ZbusLaunch a) {
   using V4 = typename Mfma<T>::V4;
+  const int Kp = net.Kp, Np = net.Np;
   __shared__ T As[2][ZB_BK][ZB_BM + ZB_PAD];
   __shared__ T Bs[2][ZB_BK][ZB_BN + ZB_PAD];
-  const int tile_n = blockIdx.x, tile_m = blockIdx.y;
+  // Workgroups are dealt to the 8 XCDs round robin (workgroup id mod 8).  When
+  // the tile count divides by 8, XCD x gets the contiguous tile range
+  // [x T/8, (x+1) T/8) in row-major tile order, so the R rows of a tile row
+  // are read into one XCD's L2 and W streams through each L2 once.
+  const int nt = Np / ZB_BN, ntiles = gridDim.x;
+  const int id = blockIdx.x;
+  const int lin = (ntiles & 7) == 0 ? (id & 7) * (ntiles >> 3) + (id >> 3) : id;
+  const int tile_n = lin % nt, tile_m = lin / nt;
   const int row0 = tile_m * ZB_BM, col0 = tile_n * ZB_BN;
   const int t = threadIdx.x;
   {
@@ -232,7 +240,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
     if (t < ZB_BM && row0 + t < a.batch) act = a.active[row0 + t];
     if (!__syncthreads_or(act)) return;
   }
-  const int Kp = net.Kp, Np = net.Np;
   const T* R = reinterpret_cast<const T*>(a.r);
   const int lane = t & (WAVE - 1), wave = t / WAVE;
   const int wm = wave >> 1, wn = wave & 1;
@@ -366,7 +373,7 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
         if (a.count_host[it - 1] == 0) break;
       }
       if (it == a.max_iter) break;
-      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt, mt), dim3(256), 0, s, d, W, a);
+      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
       PFX_HIP(hipGetLastError());
     }
   } catch (...) {
