@@ -408,7 +408,7 @@ def main() -> int:
     ap.add_argument("--workload", default="tx2000", choices=["tx2000", "tx30", "feeder", "adjoint", "serving"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
-    ap.add_argument("--cpu-samples", type=int, default=96)
+    ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counters", action="store_true",
                     help="one launch per precision plus a calibration copy, for rocprofv3 --pmc runs")
