@@ -103,17 +103,27 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
     const unsigned i = (unsigned)(sl * WAVE + lane);
     const int4 nd = cld(net.node, i);
     const double2 c = cld(net.c, i);
-    const int e = nd.x & (WYE_BIT - 1);
-    D2 sw = {0.0, 0.0}, sx = {0.0, 0.0}, sp = {0.0, 0.0};
-    if (nd.x & WYE_BIT) sw = ld2(SW, (unsigned)e);
-    if (nd.y >= 0) {
-      sx = ld2(SD, (unsigned)e);
-      sp = ld2(SD, (unsigned)nd.w);
-    }
     double yr = c.x, yi = c.y;
     const int o = cld(net.y.off, (unsigned)sl);
     const int wd = cld(net.y.width, (unsigned)sl);
-    for (int p = 0; p < wd; p += 4) {
+    int p = 0;
+    for (; p + 8 <= wd; p += 8) {  // eight entries in flight per round while they last
+      double2 g[8];
+      int cj[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
+        g[u] = cld(net.y.val, q);
+        cj[u] = cld(net.y.col, q);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const D2 x = vs[cj[u]];
+        yr += g[u].x * x.x - g[u].y * x.y;
+        yi += g[u].x * x.y + g[u].y * x.x;
+      }
+    }
+    if (p < wd) {  // widths are multiples of 4: at most one round of four remains
       double2 g[4];
       int cj[4];
 #pragma unroll
@@ -128,6 +138,13 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
         yr += g[u].x * x.x - g[u].y * x.y;
         yi += g[u].x * x.y + g[u].y * x.x;
       }
+    }
+    const int e = nd.x & (WYE_BIT - 1);
+    D2 sw = {0.0, 0.0}, sx = {0.0, 0.0}, sp = {0.0, 0.0};
+    if (nd.x & WYE_BIT) sw = ld2(SW, (unsigned)e);
+    if (nd.y >= 0) {
+      sx = ld2(SD, (unsigned)e);
+      sp = ld2(SD, (unsigned)nd.w);
     }
     if (i < (unsigned)nN) {
       const D2 v = vs[i];
