@@ -116,9 +116,9 @@ _CSRC = "paper_2605_14103_amd/csrc/"
 # Sources whose change invalidates a committed counter summary, per kernel family.
 TRAFFIC_SOURCES = {
     "nr": tuple(_CSRC + f for f in ("nr_kernels.hip", "device_ops.hpp", "tx.hpp", "tx_network.cpp", "factor.cpp",
-                                    "sell.hpp", "sell.cpp")),
+                                    "sell.hpp", "sell.cpp", "api.cpp", "api_tx.cpp")),
     "zbus": tuple(_CSRC + f for f in ("zbus_kernels.hip", "device_ops.hpp", "dist.hpp", "dist_network.cpp",
-                                      "sell.hpp", "sell.cpp")),
+                                      "sell.hpp", "sell.cpp", "api.cpp", "api_dist.cpp")),
 }
 
 

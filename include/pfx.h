@@ -62,8 +62,8 @@ typedef struct pf_opts {
   int32_t max_newton;         /* Newton updates at most, default 20 */
   int32_t gmres_restart;      /* Krylov dimension per GMRES cycle, 1..64, default 30 */
   int32_t gmres_max_restarts; /* GMRES cycles per Newton step at most, default 10 */
-  double gmres_rtol;          /* preconditioned residual reduction, default 1e-6 (0 = by precision:
-                                 1e-6 in PF_FP64, 1e-4 in PF_MIXED) */
+  double gmres_rtol;          /* preconditioned residual reduction of each Newton step's GMRES
+                                 solve (inexact Newton), default 1e-3 (0 = the default) */
   double diverge;             /* a scenario whose mismatch exceeds this is abandoned, default 1e6 */
   int32_t zbus_max_iter;      /* fixed-point updates at most, default 100 */
   /* network set-up (read by the *_network_create calls only) */

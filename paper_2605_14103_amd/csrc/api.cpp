@@ -63,7 +63,10 @@ pf_opts resolve_opts(const pf_opts* o) {
   require(r.max_newton >= 0 && r.max_newton <= 1000, "max_newton must be 0..1000");
   require(r.gmres_restart >= 1 && r.gmres_restart <= 64, "gmres_restart must be 1..64");
   require(r.gmres_max_restarts >= 1 && r.gmres_max_restarts <= 1000, "gmres_max_restarts must be 1..1000");
-  if (r.gmres_rtol == 0) r.gmres_rtol = r.precision == PF_MIXED ? 1e-4 : 1e-6;
+  // Inexact Newton: each linear solve only has to cut the preconditioned
+  // residual by 1e-3; the FP64 mismatch test decides convergence, so the
+  // answer is unchanged while the GMRES steps per Newton step drop.
+  if (r.gmres_rtol == 0) r.gmres_rtol = 1e-3;
   require(r.gmres_rtol > 0 && r.gmres_rtol < 1, "gmres_rtol must be in (0, 1)");
   require(r.diverge > 0, "diverge must be positive");
   require(r.zbus_max_iter >= 0 && r.zbus_max_iter <= 100000, "zbus_max_iter must be 0..100000");

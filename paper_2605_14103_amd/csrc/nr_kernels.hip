@@ -263,8 +263,9 @@ __device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (
 // the explicit factor passes E1 (rows into `aux` / the core right-hand side
 // into `tmp`), E2 (dense core into aux past c), E3 (rows in matrix order, read
 // from aux).  x holds the right-hand side in matrix order; aux (N entries)
-// must not overlap it.  Two barriers; the caller places one before aux or tmp
-// is written again.
+// must not overlap it.  x is read only before the first barrier.  Two
+// barriers (one when the core is empty); the caller places one before aux or
+// tmp is written again.
 template <typename T, int BLOCK, int KB, int OFF, int K>
 __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K]) {
   constexpr int NW = BLOCK / WAVE;
@@ -327,7 +328,7 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
     }
     aux[f.c + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
-  __syncthreads();
+  if (f.k > 0) __syncthreads();  // with no core, E3 reads only what E1 wrote
   T acc[KB];
   sell_slots_dot<KB, NW>(f.e3, aux, acc);
 #pragma unroll
@@ -358,7 +359,9 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
   __syncthreads();
   efac_apply<T, BLOCK, KB, 0>(net.bp, X, Y, s.tmp, w);
   if (npq > 0) {
-    __syncthreads();
+    // X was last read before the first barrier of the B' passes, so z_Theta
+    // may overwrite it at once; the barrier below also orders the B' passes'
+    // reads of Y before Y is written again.
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);
