@@ -270,14 +270,28 @@ template <typename T, int BLOCK, int KB, int OFF, int K>
 __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K]) {
   constexpr int NW = BLOCK / WAVE;
   const int lane = lane_id(), wv = wave_id();
-#pragma unroll
+  // (kept rolled: the loop indexes no register array, and its body is large)
+#pragma unroll 1
   for (int q = 0; q < KB; ++q) {
     // (entry offset, width, first row) of this wave's q-th slice; width 0 past its list
     const int4 t = cld(reinterpret_cast<const int4*>(f.e1_wave), (unsigned)(wv * KB + q));
     if (t.y > 0) {
       const int r = cld(f.e1_row, (unsigned)(t.z + lane));
       T acc = 0;
-      for (int p = 0; p < t.y; p += 4) {  // widths are multiples of 4
+      int p = 0;
+      for (; p + 8 <= t.y; p += 8) {  // eight entries in flight per round while they last
+        T v[8];
+        int c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const unsigned qq = (unsigned)(t.x + (p + u) * WAVE + lane);
+          v[u] = cld(f.e1.val, qq);
+          c[u] = cld(f.e1.col, qq);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u] * x[c[u]];
+      }
+      if (p < t.y) {  // widths are multiples of 4: at most one round of four remains
         T v[4];
         int c[4];
 #pragma unroll
@@ -599,38 +613,44 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
   for (int k = 0; k < K; ++k) ws.st(xpl, k, 0.0);
   for (int cycle = 0; cycle < max_restarts && !done; ++cycle) {
     *work += (cycle > 0 ? bm.jvp() : 0.0) + bm.pre() + bm.m8 + bm.wm;
-    if (cycle == 0) {
-#pragma unroll
-      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k);
-    } else {
-#pragma unroll
-      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(xpl, k);
-      apply_a(w);
-#pragma unroll
-      for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k) - w[k];
-    }
-    apply_m(w);
-    T ss = 0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) ss += w[k] * w[k];
-    const T beta = sqrt(block_sum<T, BLOCK>(ss, next_part()));
-    if (cycle == 0) beta0 = beta;
-    if (!(beta > rtol * beta0) || beta == (T)0) {
-      done = !(beta > rtol * beta0);
-      break;
-    }
-    const T ib = (T)1 / beta;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      w[k] *= ib;
-      basis.st(0, k, w[k]);
-    }
-    if (threadIdx.x == 0) s.gres[0] = beta;
     int steps = 0;
-    T res = beta;
-    for (int j = 0; j < R; ++j) {
-      apply_a(w);
+    T res = 0;
+    bool stop = false;
+    // Step -1 starts the cycle (w = M^-1 (b - A x)); steps j >= 0 are Arnoldi
+    // steps.  One call site for A and one for M^-1 keeps the loop's code
+    // compact (they are inlined).
+    for (int j = -1; j < R; ++j) {
+      if (j < 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(cycle == 0 ? bpl : xpl, k);
+      }
+      if (j >= 0 || cycle > 0) apply_a(w);
+      if (j < 0 && cycle > 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k) - w[k];
+      }
       apply_m(w);
+      if (j < 0) {
+        T ss = 0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) ss += w[k] * w[k];
+        const T beta = sqrt(block_sum<T, BLOCK>(ss, next_part()));
+        if (cycle == 0) beta0 = beta;
+        if (!(beta > rtol * beta0) || beta == (T)0) {
+          done = !(beta > rtol * beta0);
+          stop = true;
+          break;
+        }
+        const T ib = (T)1 / beta;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          w[k] *= ib;
+          basis.st(0, k, w[k]);
+        }
+        if (threadIdx.x == 0) s.gres[0] = beta;
+        res = beta;
+        continue;
+      }
       T ss0 = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) ss0 += w[k] * w[k];
@@ -690,6 +710,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
         basis.st(j + 1, k, w[k]);
       }
     }
+    if (stop) break;
     total += steps;
     *work += (steps + 2) * bm.wm;
     // y = H^-1 g (upper triangular after the rotations)

@@ -3,7 +3,9 @@
 //
 // Internal bus order.  Buses are renumbered so that PQ buses come first, then
 // PV buses, then the slack (each group by decreasing degree, so that rows of
-// similar length share a slice).  With n buses, nth = n - 1 and npq PQ buses,
+// similar length share a slice; the full 64-bus groups of PQ buses are dealt
+// to the waves of a workgroup in a zigzag so that each wave gets a like share
+// of long rows).  With n buses, nth = n - 1 and npq PQ buses,
 // Theta is internal buses 0..nth-1 and Q is 0..npq-1.  The kernels hold the
 // Newton state x = [theta over Theta ; |V| over Q] (eq. (1)) bus-major: two
 // planes of nbp (padded bus count) entries, angle of bus i at i and magnitude

@@ -56,7 +56,7 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
     e[0] = h1.off[s];
     e[1] = h1.width[s];
     e[2] = s * SLICE;
-    load[best] += h1.width[s] / 4 + 1;   // rounds of four entries, plus the slice's own overhead
+    load[best] += (h1.width[s] + 7) / 8 + 1;   // rounds of up to eight entries, plus the slice's own overhead
   }
   // E3: one row per matrix row (bus order), padded to nbp rows.
   std::vector<Row> rows3(nbp);
@@ -218,6 +218,24 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
   auto by_degree = [&](int a, int b) { return degree[a] != degree[b] ? degree[a] > degree[b] : a < b; };
   std::sort(pq.begin(), pq.end(), by_degree);
   std::sort(pv.begin(), pv.end(), by_degree);
+  int blk = 0, kbs = 0;
+  nr_shape(n_bus, &blk, &kbs);
+  {
+    // Wave w of a workgroup owns the 64-bus slices k NW + w.  Deal the full
+    // 64-bus groups of PQ buses (widest rows first) to the waves in a zigzag
+    // (0 .. NW-1, then NW-1 .. 0, ...), so that every wave gets a like share
+    // of long rows in each sliced pass.  A last incomplete row of groups keeps
+    // the plain order, and buses never leave the PQ range.
+    const int nw = blk / 64, full = (int)pq.size() / 64;
+    std::vector<int> dealt(pq);
+    for (int g = 0; g < full; ++g) {
+      const int k = g / nw, r = g % nw;
+      const bool whole_row = (k + 1) * nw <= full;
+      const int slice = k * nw + ((k % 2 == 1 && whole_row) ? nw - 1 - r : r);
+      std::copy(pq.begin() + (size_t)g * 64, pq.begin() + (size_t)g * 64 + 64, dealt.begin() + (size_t)slice * 64);
+    }
+    pq.swap(dealt);
+  }
 
   auto net = std::make_unique<TxNetwork>();
   net->ctx = ctx;
@@ -232,7 +250,8 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
   net->int2ext.push_back(slack);
   net->ext2int.assign(n_bus, 0);
   for (int i = 0; i < n_bus; ++i) net->ext2int[net->int2ext[i]] = i;
-  nr_shape(n_bus, &net->block, &net->kb);
+  net->block = blk;
+  net->kb = kbs;
   net->nbp = net->block * net->kb;
   const int nbp = net->nbp, nth = net->nth, npq = net->npq;
 
