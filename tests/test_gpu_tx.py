@@ -258,3 +258,23 @@ def test_autograd_matches_finite_differences(ctx):
             assert abs(fd - gq[c, k]) <= 1e-5 * scale
         assert gp[c, grid.slack] == 0 and np.all(gq[c, grid.bus_type != tx.PQ] == 0)
     net.close()
+
+
+# One grid per workgroup shape of the solve kernels: (64 threads, 1 slot),
+# (64, 4), (256, 4), (512, 8) and (1024, 8); the 2000-bus grid above covers
+# (256, 8).  Three scenarios each (the 8000-bus grid checks one against the
+# oracle, whose sparse solve takes seconds there).
+@pytest.mark.parametrize("n_bus,n_check", [(50, 3), (200, 3), (700, 3), (3000, 3), (8000, 1)])
+def test_every_workgroup_shape(ctx, n_bus, n_check):
+    from paper_2605_14103_amd import pf
+    cfg = tx.TxConfig(f"tx{n_bus}", n_bus=n_bus, n_pv=max(1, (3 * n_bus) // 20), n_branch=(13 * n_bus) // 10,
+                      batch=3, seed=n_bus, perturbation="uniform", spread=0.2)
+    say(cfg.name)
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    for precision in ("fp64", "mixed"):
+        res = _solve(net, batch, precision=pf.precision(precision))
+        assert res.converged.cpu().numpy().all()
+        _check_against_oracle(grid, batch, res, np.arange(n_check), precision)
+    net.close()

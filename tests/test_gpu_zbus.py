@@ -106,3 +106,18 @@ def test_zero_load_and_caps(ctx):
     import torch
     assert torch.equal(r2.v[0], full.v[0]) and torch.equal(r2.v[2], full.v[2])
     net.close()
+
+
+def test_large_feeder_many_slots(ctx):
+    """A 700-bus feeder (2097 free nodes): the residual kernel's widest slot
+    template (more than 1024 free nodes per workgroup) and several GEMM column
+    tiles with a ragged last one."""
+    from paper_2605_14103_amd import pf
+    cfg = fdm.FeederConfig("feeder700", n_bus=700, max_depth=30, batch=6, seed=700)
+    fd = fdm.make_feeder(cfg)
+    batch = fdm.make_batch(fd, cfg)
+    net = pf.DistNetwork.from_feeder(ctx, fd)
+    for precision in ("fp64", "mixed"):
+        res = _solve(net, batch, precision=pf.precision(precision))
+        _check(fd, batch, res, np.arange(batch.batch), f"feeder700 {precision}")
+    net.close()
