@@ -143,10 +143,12 @@ pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* 
  * all Newton steps), converged[batch] (1 when max |F| <= tol),
  * final_mismatch[batch] (max |F| at v_out), work_bytes[batch] (algorithmic
  * HBM bytes of the scenario's solve under the byte model: per Jacobian-vector
- * product 2wm + 32n, per preconditioner application 2wm + 8n, per Arnoldi
- * step j (4j + 6)wm, per GMRES cycle start 8m + wm and end (k + 2)wm for k
- * steps, per mismatch evaluation 32n + 16m, per Newton update 16m, with
- * w = 8 (PF_FP64) or 4 (PF_MIXED) and m = |Theta| + |Q|).  Optional outputs
+ * product 2wm + 4wn (V and I in the inner solve's precision), per
+ * preconditioner application 2wm + 8n, per Gram-Schmidt pass of Arnoldi step
+ * j (2j + 3)wm (a second pass, when taken, counts again), per GMRES cycle
+ * start 8m + wm and end (k + 2)wm for k steps, per mismatch evaluation
+ * 32n + 16m, per Newton update 16m, with w = 8 (PF_FP64) or 4 (PF_MIXED) and
+ * m = |Theta| + |Q|).  Optional outputs
  * may be null: gmres_iters, final_mismatch, work_bytes.  batch may be 0.
  * Errors: PF_INVALID_ARG (ld < n_bus, batch < 0, bad options),
  * PF_OUT_OF_MEMORY, PF_HIP_ERROR. */

@@ -184,6 +184,71 @@ struct Ws {
   __device__ __forceinline__ void st(int a, int k, double v) const {
     bst<WS_POLICY>(b, v, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
   }
+  // The mismatch's V, I and 1/|V| as the inner solve reads them: FP64 planes,
+  // or for an FP32 inner solve FP32 copies in the same planes (V and I as
+  // (re, im) pairs in one 8-byte slot of the VRE and IRE planes, 1/|V| in the
+  // first half of the IVM slot), which halves their bytes per product.
+  template <typename T>
+  __device__ __forceinline__ void put_vi(int k, double vr, double vi, double ivm) const {
+    if constexpr (sizeof(T) == 4) {
+      st(VRE, k, pack2(vr, vi));
+      bst<WS_POLICY>(b, (float)ivm, threadIdx.x * 8u, (unsigned)(IVM * NBP + k * BLOCK) * 8u);
+    } else {
+      st(VRE, k, vr);
+      st(VIM, k, vi);
+      st(IVM, k, ivm);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void put_i(int k, double ir, double ii) const {
+    if constexpr (sizeof(T) == 4) {
+      st(IRE, k, pack2(ir, ii));
+    } else {
+      st(IRE, k, ir);
+      st(IIM, k, ii);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void get_v(int k, T& re, T& im) const {
+    if constexpr (sizeof(T) == 4) {
+      unpack2(ld(VRE, k), re, im);
+    } else {
+      re = ld(VRE, k);
+      im = ld(VIM, k);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void get_i(int k, T& re, T& im) const {
+    if constexpr (sizeof(T) == 4) {
+      unpack2(ld(IRE, k), re, im);
+    } else {
+      re = ld(IRE, k);
+      im = ld(IIM, k);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ T get_ivm(int k) const {
+    if constexpr (sizeof(T) == 4) {
+      return bld<float, WS_POLICY>(b, threadIdx.x * 8u, (unsigned)(IVM * NBP + k * BLOCK) * 8u);
+    } else {
+      return ld(IVM, k);
+    }
+  }
+
+ private:
+  static __device__ __forceinline__ double pack2(double x, double y) {
+    const float f[2] = {(float)x, (float)y};
+    double d;
+    __builtin_memcpy(&d, f, 8);
+    return d;
+  }
+  template <typename T>
+  static __device__ __forceinline__ void unpack2(double d, T& x, T& y) {
+    float f[2];
+    __builtin_memcpy(f, &d, 8);
+    x = f[0];
+    y = f[1];
+  }
 };
 
 // The Krylov basis of one scenario: vectors of MP = 2 NBP entries of T.
@@ -367,7 +432,7 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     const unsigned i = row<BLOCK>(k);
-    const T v = w[k] * (T)ws.ld(IVM, k);
+    const T v = w[k] * ws.template get_ivm<T>(k);
     if (i < nth) X[i] = v;
   }
   __syncthreads();
@@ -388,7 +453,7 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);
-      const T t = (w[KB + k] - gz[k]) * (T)ws.ld(IVM, k);
+      const T t = (w[KB + k] - gz[k]) * ws.template get_ivm<T>(k);
       if (i < npq) Y[i] = t;
     }
     __syncthreads();
@@ -411,9 +476,8 @@ __device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     const unsigned i = row<BLOCK>(k);
-    const T a = w[KB + k] * (T)ws.ld(IVM, k);
-    vre[k] = (T)ws.ld(VRE, k);
-    vim[k] = (T)ws.ld(VIM, k);
+    const T a = w[KB + k] * ws.template get_ivm<T>(k);
+    ws.template get_v<T>(k, vre[k], vim[k]);
     T2 d;
     d.x = vre[k] * a - vim[k] * w[k];
     d.y = vim[k] * a + vre[k] * w[k];
@@ -423,14 +487,12 @@ __device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB
   // The own bus's I is fetched one slot ahead, so its HBM latency overlaps the
   // previous slot's row.
   const int wv = wave_id();
-  double nIr = ws.ld(IRE, 0), nIi = ws.ld(IIM, 0);
+  T nIr, nIi;
+  ws.template get_i<T>(0, nIr, nIi);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const T Ir = (T)nIr, Ii = (T)nIi, vr = vre[k], vi = vim[k];
-    if (k + 1 < KB) {
-      nIr = ws.ld(IRE, k + 1);
-      nIi = ws.ld(IIM, k + 1);
-    }
+    const T Ir = nIr, Ii = nIi, vr = vre[k], vi = vim[k];
+    if (k + 1 < KB) ws.template get_i<T>(k + 1, nIr, nIi);
     T dIr = 0, dIi = 0;
     sell_row4(net.yT, k * NW + wv, [&](T2 y, int c) {
       const T2 d = dv[c];
@@ -527,9 +589,7 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
     double2 v;
     v.x = vm * cs;
     v.y = vm * sn;
-    ws.st(VRE, k, v.x);
-    ws.st(VIM, k, v.y);
-    ws.st(IVM, k, 1.0 / vm);
+    ws.template put_vi<T>(k, v.x, v.y, 1.0 / vm);
     vs[i] = v;
   }
   __syncthreads();
@@ -551,8 +611,7 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
     });
     const unsigned i = row<BLOCK>(k);
     const double2 v = vs[i];
-    ws.st(IRE, k, Ir);
-    ws.st(IIM, k, Ii);
+    ws.template put_i<T>(k, Ir, Ii);
     const double ft = i < nth ? v.x * Ir + v.y * Ii - pk : 0.0;
     const double fv = i < npq ? v.y * Ir - v.x * Ii - qk : 0.0;
     ws.st(FP, k, ft);
@@ -564,14 +623,17 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
 }
 
 // Algorithmic HBM bytes of one scenario (the byte model reported with the
-// solve): with w = sizeof(T), per Jacobian-vector product 2 w m + 32 n, per
+// solve): with w = sizeof(T), per Jacobian-vector product 2 w m + 4 w n, per
 // preconditioner application 2 w m + 8 n, per Gram-Schmidt pass of Arnoldi
 // step j (against j + 1 vectors) (2 j + 3) w m, per cycle start 8 m + w m,
 // per cycle end (k + 2) w m, per mismatch evaluation 32 n + 16 m and per
 // Newton update 16 m.
 struct ByteModel {
   double wm, m8, n8;
-  __device__ double jvp() const { return 2 * wm + 4 * n8; }
+  // V and I (four reals per bus) read by a Jacobian-vector product: FP64, or
+  // their FP32 copies for an FP32 inner solve
+  double vi_n;
+  __device__ double jvp() const { return 2 * wm + vi_n; }
   __device__ double pre() const { return 2 * wm + n8; }
   __device__ double orth_pass(int j) const { return (2.0 * j + 3.0) * wm; }
   __device__ double mismatch() const { return 4 * n8 + 2 * m8; }
@@ -793,7 +855,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   for (;;) {
     fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW);
     const TxDev<T> net = load_desc(netp);
-    const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n};
+    const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n, 4.0 * sizeof(T) * n};
     work += bm.mismatch();
     par ^= 1;
     if (!(fnorm <= a.diverge)) break;
@@ -826,8 +888,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const unsigned i = row<BLOCK>(k);
       if ((int)i < n) {
         const unsigned e = (unsigned)cld(net.int2ext, i) * 16u;
-        bst(vout, ws.ld(VRE, k), e, 0);
-        bst(vout, ws.ld(VIM, k), e, 8);
+        // V of the last iterate, formed exactly as the last mismatch formed it
+        double sn, cs;
+        sincos(ws.ld(TH, k), &sn, &cs);
+        const double vm = ws.ld(VM, k);
+        bst(vout, vm * cs, e, 0);
+        bst(vout, vm * sn, e, 8);
       }
     }
   }
@@ -1029,7 +1095,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   int its;
   {
     const TxDev<double> net = load_desc(netp);
-    const ByteModel bm{8.0 * net.m, 8.0 * net.m, 8.0 * n};
+    const ByteModel bm{8.0 * net.m, 8.0 * net.m, 8.0 * n, 32.0 * n};
     its = gmres_solve<double, BLOCK, KB>(apply_jt, apply_mt, ws, FP, DXP, basis, R, a.max_restarts, a.rtol, s,
                                          &ok, bm, &work);
   }
