@@ -319,7 +319,8 @@ def bench_serving(n_requests: int, lam: float) -> dict:
         return b.s_wye, b.s_delta
 
     out = {}
-    for prec in ("fp64", "mixed"):
+    half = wsv.make_trace(wsv.SERVING, n_requests=n_requests // 2, lam=lam / 2)
+    for prec, tr, key in (("fp64", trace, "fp64"), ("mixed", trace, "mixed"), ("fp64", half, "fp64_half_load")):
         ctx = pf.Context(0)
         nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
                 pf.DistNetwork.from_feeder(ctx, fd)]
@@ -331,12 +332,13 @@ def bench_serving(n_requests: int, lam: float) -> dict:
         warm = [r for r in wsv.make_trace(wsv.SERVING, n_requests=30, lam=lam) if r.n_scen <= 8][:6]
         serve.replay(engines, warm, inputs, speed=100.0)
         t = time.perf_counter()
-        st = serve.replay(engines, trace, inputs)
+        st = serve.replay(engines, tr, inputs)
         summ = st.summary()
         summ["wall_s"] = time.perf_counter() - t
         summ["engines"] = [e.info() for e in engines]
-        out[prec] = summ
-        print(f"[serving {prec}] {summ['requests']} requests, {summ['solves_per_s']:.0f} solves/s, "
+        summ["lambda_per_s"] = lam / 2 if key.endswith("half_load") else lam
+        out[key] = summ
+        print(f"[serving {key}] {summ['requests']} requests, {summ['solves_per_s']:.0f} solves/s, "
               f"p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
         for e in engines:
             e.close()
@@ -351,7 +353,50 @@ def bench_serving(n_requests: int, lam: float) -> dict:
             "config": {"workload": f"serving mix: Poisson lambda={lam}/s, {n_requests} requests over tx30, "
                                    f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8"},
             "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
-            "fp64": out["fp64"], "mixed": out["mixed"]}
+            "fp64": out["fp64"], "mixed": out["mixed"], "fp64_half_load": out["fp64_half_load"]}
+
+
+def bench_sweep(steps: int, warmup: int) -> dict:
+    """Solve time against batch size (2000-bus grid and 900-node feeder, both precisions)."""
+    import torch
+
+    from paper_2605_14103_amd import pf
+    from workloads import feeder as fdm
+    from workloads import transmission as tx
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rows = []
+    ctx = pf.Context(0)
+    grid = tx.make_grid(tx.TX2000)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    for B in (1, 16, 64, 256, 1024, 4096):
+        batch = tx.make_batch(grid, tx.TX2000, batch=B)
+        p, q, vm = dev(batch.p_inj), dev(batch.q_inj), dev(batch.vm_set)
+        for prec in ("fp64", "mixed"):
+            out = net.solve(p, q, vm, precision=pf.precision(prec))
+            ms, _, out = time_steps(lambda: net.solve(p, q, vm, out=out, precision=pf.precision(prec)), steps, warmup)
+            conv = int(out.converged.sum().item())
+            rows.append({"workload": "tx2000", "batch": B, "precision": prec, "ms": float(ms.mean()),
+                         "solves_per_s": conv / (float(ms.mean()) * 1e-3), "converged": conv})
+            print(f"[sweep] tx2000 B={B} {prec} {ms.mean():.3f} ms", file=sys.stderr, flush=True)
+    net.close()
+    fd = fdm.make_feeder(fdm.FEEDER300)
+    dnet = pf.DistNetwork.from_feeder(ctx, fd)
+    for B in (1, 16, 64, 256, 1024, 4096, 16384):
+        batch = fdm.make_batch(fd, fdm.FEEDER300, batch=B)
+        sw, sd = dev(batch.s_wye), dev(batch.s_delta)
+        for prec in ("fp64", "mixed"):
+            ms, _, out = time_steps(lambda: dnet.solve(sw, sd, precision=pf.precision(prec)), steps, warmup)
+            conv = int(out.converged.sum().item())
+            rows.append({"workload": "feeder300", "batch": B, "precision": prec, "ms": float(ms.mean()),
+                         "solves_per_s": conv / (float(ms.mean()) * 1e-3), "converged": conv})
+            print(f"[sweep] feeder300 B={B} {prec} {ms.mean():.3f} ms", file=sys.stderr, flush=True)
+    dnet.close()
+    ctx.close()
+    best = max(r["solves_per_s"] for r in rows if r["workload"] == "tx2000" and r["precision"] == "fp64")
+    return {"metric": METRIC, "value": best, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": {"workload": "batch sweep: tx2000 B=1..4096, feeder300 B=1..16384"},
+            "sweep": rows}
 
 
 def counters_run(workload: str) -> dict:
@@ -405,7 +450,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="tx2000", choices=["tx2000", "tx30", "feeder", "adjoint", "serving"])
+    ap.add_argument("--workload", default="tx2000",
+                    choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--cpu-samples", type=int, default=256)
@@ -431,6 +477,8 @@ def main() -> int:
         line = bench_adjoint(a.steps, a.warmup)
     elif a.workload == "serving":
         line = bench_serving(a.requests, a.lam)
+    elif a.workload == "sweep":
+        line = bench_sweep(a.steps, a.warmup)
     else:
         line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
     print(json.dumps(line), flush=True)
