@@ -297,7 +297,7 @@ def bench_adjoint(steps: int, warmup: int) -> dict:
     return line
 
 
-def bench_serving(n_requests: int, lam: float) -> dict:
+def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1)) -> dict:
     """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder)."""
     from paper_2605_14103_amd import pf, serve
     from workloads import feeder as fdm
@@ -325,7 +325,6 @@ def bench_serving(n_requests: int, lam: float) -> dict:
         nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
                 pf.DistNetwork.from_feeder(ctx, fd)]
         budgets = (1 << 30, 24 << 30, 4 << 30)
-        streams = (1, 2, 1)
         engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec))
                    for n, b, s in zip(nets, budgets, streams)]
         # warm-up: one small request per engine (code objects, first launches)
@@ -454,6 +453,8 @@ def main() -> int:
                     choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
+    ap.add_argument("--streams", default="1,2,1",
+                    help="serving: HIP streams of the 30-bus, 2000-bus and feeder engines")
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--counters", action="store_true",
@@ -476,7 +477,7 @@ def main() -> int:
     elif a.workload == "adjoint":
         line = bench_adjoint(a.steps, a.warmup)
     elif a.workload == "serving":
-        line = bench_serving(a.requests, a.lam)
+        line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")))
     elif a.workload == "sweep":
         line = bench_sweep(a.steps, a.warmup)
     else:
