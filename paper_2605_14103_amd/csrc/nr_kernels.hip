@@ -12,8 +12,9 @@
 //     the vector being gathered (V for Ybus V, dV for the Jacobian-vector
 //     product, the preconditioner's right-hand sides), reduction partials, the
 //     packed Hessenberg matrix and the Givens rotations;
-//   * HBM (scenario-major workspace): theta, |V|, 1/|V|, V, I, P, Q, F, the
-//     Newton step and the Krylov basis.
+//   * HBM (scenario-major workspace): theta, |V|, 1/|V|, V, I (the last three
+//     as FP32 copies when the inner solve runs in FP32), P, Q, F, the Newton
+//     step and the Krylov basis.
 // Network data (sliced Ybus, G, the explicit factors of B' and B'') is shared
 // by all workgroups and read through the caches; it is never written during a
 // launch, so it is read through the constant address space.
