@@ -331,10 +331,18 @@ __device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (
 // from aux).  x holds the right-hand side in matrix order; aux (N entries)
 // must not overlap it.  x is read only before the first barrier.  Two
 // barriers (one when the core is empty); the caller places one before aux or
-// tmp is written again.
+// tmp is written again.  A factor applied directly (f.direct) reads x
+// throughout and has no barrier: the caller places one before x is written.
 template <typename T, int BLOCK, int KB, int OFF, int K>
 __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K]) {
   constexpr int NW = BLOCK / WAVE;
+  if (f.direct) {  // one sliced pass over A^-1 itself; no barrier, x read throughout
+    T acc[KB];
+    sell_slots_dot<KB, NW>(f.inv, x, acc);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) out[OFF + k] = acc[k];
+    return;
+  }
   const int lane = lane_id(), wv = wave_id();
   // (kept rolled: the loop indexes no register array, and its body is large)
 #pragma unroll 1
@@ -439,9 +447,10 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
   __syncthreads();
   efac_apply<T, BLOCK, KB, 0>(net.bp, X, Y, s.tmp, w);
   if (npq > 0) {
-    // X was last read before the first barrier of the B' passes, so z_Theta
-    // may overwrite it at once; the barrier below also orders the B' passes'
-    // reads of Y before Y is written again.
+    // X was last read before the first barrier of the B' passes (unless B' is
+    // applied directly), so z_Theta may overwrite it at once; the barrier
+    // below also orders the B' passes' reads of Y before Y is written again.
+    if (net.bp.direct) __syncthreads();
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);

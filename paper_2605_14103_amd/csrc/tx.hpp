@@ -38,6 +38,11 @@ struct EfDev {
   const int* e1_wave;    // [n_waves * kb][4]: entry offset, width, first row id index, 0
   Sell<T> e3;
   const T* sinv;         // S^-1 (k x k) in packs [l / P][i][P], P = 16 / sizeof(T)
+  // With no dense core the inverse itself may be sparse enough to apply in one
+  // pass: then `direct` is 1 and `inv` holds A^-1 by rows in bus order, with
+  // columns in matrix order (E1, E2 and E3 are not used).
+  int direct;
+  Sell<T> inv;
 };
 
 template <typename T>
@@ -64,6 +69,8 @@ struct TxDev {
 
 struct EfBuffers {
   ExplicitFactor host;
+  bool direct = false;
+  SellBuffers inv;
   SellBuffers e1, e3;
   DeviceBuffer e1_row, e1_wave, sinv64, sinv32;
   template <typename T>

@@ -65,6 +65,31 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
   SellHost h3 = build_sell(rows3, 4);
   upload_sell(ctx, h1, false, f.e1);
   upload_sell(ctx, h3, false, f.e3);
+  // With no core, A^-1 = E3 E1 (times the permutation) may stay sparse: if its
+  // sliced rows are not much longer than E1's and E3's together, it is
+  // applied in one pass with no barrier inside.
+  f.direct = false;
+  if (E.k == 0) {
+    std::vector<Row> rowsd(nbp);
+    long nnz = 0;
+    for (int i = 0; i < N; ++i) {
+      std::map<int, double> acc;
+      for (auto [p, v3] : E.e3[E.pinv[i]])
+        for (auto [j, v1] : E.e1[p]) acc[E.perm[j]] += v3 * v1;
+      for (auto [c, v] : acc) rowsd[i].push_back({c, v, 0.0});
+      nnz += (long)acc.size();
+    }
+    SellHost hd = build_sell(rowsd, 4);
+    auto padded = [](const SellHost& h) {
+      long t = 0;
+      for (size_t q = 0; q < h.width.size(); ++q) t += 64L * h.width[q];
+      return t;
+    };
+    if (2 * padded(hd) <= 3 * (padded(h1) + padded(h3))) {
+      upload_sell(ctx, hd, false, f.inv);
+      f.direct = true;
+    }
+  }
   f.e1_row = upload(ctx, rid);
   f.e1_wave = upload(ctx, wave_list);
   // S^-1 in packs of P columns per row, [l / P][i][P], zero-padded (P = 2 in
@@ -150,6 +175,8 @@ EfDev<T> EfBuffers::view() const {
   d.e1_wave = e1_wave.as<int>();
   d.e3 = e3.view<T>();
   d.sinv = f64 ? sinv64.as<T>() : sinv32.as<T>();
+  d.direct = direct ? 1 : 0;
+  d.inv = direct ? inv.view<T>() : Sell<T>{nullptr, nullptr, nullptr, nullptr};
   return d;
 }
 
