@@ -658,9 +658,10 @@ struct ByteModel {
 // a breakdown.  Returns the number of Arnoldi steps; *converged tells whether
 // the tolerance was met.
 //
-// Orthogonalisation: one reduction gives <v_i, w> and ||w||^2 together, a
-// second one ||w'||^2 after the projection; a second classical Gram-Schmidt
-// pass runs when the projection leaves less than 1/64 of the norm.  Every thread applies the Givens
+// Orthogonalisation: one reduction gives <v_i, w> and ||w||^2 together;
+// ||w'||^2 after the projection is their difference unless it cancels (then a
+// second reduction); a second classical Gram-Schmidt pass runs when the
+// projection leaves less than 1/64 of the norm.  Every thread applies the Givens
 // rotations to the new Hessenberg column itself (same data, same operations),
 // so no barrier is needed after them; thread 0 alone stores H, the rotations
 // and the rotated right-hand side for later steps.
@@ -728,14 +729,18 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
       for (int k = 0; k < K; ++k) ss0 += w[k] * w[k];
       T* p1 = next_part();
       multi_dot<T, BLOCK, KB>(basis, j + 1, w, ss0, p1);
-      subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
+      const T hh1 = subtract_proj<T, BLOCK, KB>(basis, j + 1, w, p1);
       const T wn2 = part_sum<T, NW>(p1, j + 1);
-      // ||w'||^2 by its own reduction (with a good preconditioner most of w
-      // lies in the span of the basis, so ||w||^2 - sum h_i^2 would cancel)
+      // ||w'||^2 = ||w||^2 - sum h_i^2, unless that difference has cancelled
+      // below tau ||w||^2 (its relative error is then above eps / tau): then
+      // by its own reduction.  Every thread takes the same branch (the same
+      // partials, summed in the same order).
       T s1 = 0;
 #pragma unroll
       for (int k = 0; k < K; ++k) s1 += w[k] * w[k];
-      T nrm2 = block_sum<T, BLOCK>(s1, s.redn);
+      T nrm2 = wn2 - hh1;
+      constexpr T tau = sizeof(T) == 8 ? (T)1e-4 : (T)1e-3;
+      if (!(nrm2 >= tau * wn2)) nrm2 = block_sum<T, BLOCK>(s1, s.redn);
       // Second pass only when the projection removed all but 1/64 of the
       // norm: the first pass's rounding then leaves the new vector orthogonal
       // to about 64 ulp, far below the GMRES tolerance, and a pass is saved in
