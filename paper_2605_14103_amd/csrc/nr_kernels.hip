@@ -316,13 +316,58 @@ __device__ __forceinline__ void sell_slots(const Sell<V>& a, Body&& body, Done&&
   }
 }
 
-// out[k] -= or = sum over slot k's row of val * x[col], real values
+// acc[k] = sum over slot k's row of val * x[col], real values.  In FP32,
+// slots are taken in pairs whose rows advance together, so each round has
+// the loads of two rows in flight (in FP64 the extra registers cost more
+// than the overlap gains).
 template <int KB, int NW, typename T>
 __device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (&acc)[KB]) {
+  const int wv = wave_id(), lane = lane_id();
 #pragma unroll
   for (int k = 0; k < KB; ++k) acc[k] = 0;
-  sell_slots<KB, NW>(
-      a, [&](int k, T v, int c) { acc[k] += v * x[c]; }, [&](int k) { settle(acc[k]); });
+  if constexpr (KB % 2 == 0 && sizeof(T) == 4) {
+#pragma unroll
+    for (int k = 0; k < KB; k += 2) {
+      const int s0 = k * NW + wv, s1 = (k + 1) * NW + wv;
+      const int o0 = cld(a.off, (unsigned)s0), o1 = cld(a.off, (unsigned)s1);
+      const int wd0 = cld(a.width, (unsigned)s0), wd1 = cld(a.width, (unsigned)s1);
+      const int wd = wd0 > wd1 ? wd0 : wd1;
+      for (int p = 0; p < wd; p += 4) {
+        T v0[4], v1[4];
+        int c0[4], c1[4];
+        const bool r0 = p < wd0, r1 = p < wd1;   // uniform: widths are per slice
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v0[u] = v1[u] = 0;
+          c0[u] = c1[u] = 0;
+        }
+        if (r0)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const unsigned q = (unsigned)(o0 + (p + u) * WAVE + lane);
+            v0[u] = cld(a.val, q);
+            c0[u] = cld(a.col, q);
+          }
+        if (r1)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const unsigned q = (unsigned)(o1 + (p + u) * WAVE + lane);
+            v1[u] = cld(a.val, q);
+            c1[u] = cld(a.col, q);
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          acc[k] += v0[u] * x[c0[u]];
+          acc[k + 1] += v1[u] * x[c1[u]];
+        }
+      }
+      settle(acc[k]);
+      settle(acc[k + 1]);
+    }
+  } else {
+    sell_slots<KB, NW>(
+        a, [&](int k, T v, int c) { acc[k] += v * x[c]; }, [&](int k) { settle(acc[k]); });
+  }
 }
 
 // out[OFF + k] = (A^-1 x)_i for the bus slots i = t + k BLOCK (zero past N), by
