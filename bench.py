@@ -228,16 +228,19 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
     B = batch.batch
     nN = net.info["n_free"]
     runs = {}
-    for prec in ("fp64", "mixed"):
-        ms, wall, out = time_steps(lambda: net.solve(sw, sd, precision=pf.precision(prec)), steps, warmup)
+    for prec, sparse in (("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)):
+        key = prec + ("_sparse" if sparse else "")
+        ms, wall, out = time_steps(lambda: net.solve(sw, sd, precision=pf.precision(prec), zbus_sparse=sparse),
+                                   steps, warmup)
         conv = int(out.converged.sum().item())
         its = out.iters.double()
         gemm_flops = 8.0 * nN * nN * float(its.sum().item())
         mean_ms = float(ms.mean())
-        runs[prec] = {"value": conv / (mean_ms * 1e-3), "ms_per_step": mean_ms, "converged": conv,
-                      "iters_mean": float(its.mean().item()), "max_mismatch": float(out.mismatch.max().item()),
-                      "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99))},
-                      "useful_gemm_TFLOPs": gemm_flops / (mean_ms * 1e-3) / 1e12}
+        runs[key] = {"value": conv / (mean_ms * 1e-3), "ms_per_step": mean_ms, "converged": conv,
+                     "iters_mean": float(its.mean().item()), "max_mismatch": float(out.mismatch.max().item()),
+                     "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99))}}
+        if not sparse:
+            runs[key]["useful_gemm_TFLOPs"] = gemm_flops / (mean_ms * 1e-3) / 1e12
     r = runs["fp64"]
     tf = r["useful_gemm_TFLOPs"]
     line = {"metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
@@ -254,6 +257,7 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
                          "basis": "useful complex flops (8 nN^2 per scenario and iteration) over the whole "
                                   "solve time, residual kernels and launch gaps included"},
             "fp64": runs["fp64"], "mixed": runs["mixed"],
+            "sparse_variant": {"fp64": runs["fp64_sparse"], "mixed": runs["mixed_sparse"]},
             "mixed_vs_fp64": runs["mixed"]["value"] / r["value"]}
     if cpu is not None:
         line["cpu_baseline"] = cpu

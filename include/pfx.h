@@ -73,6 +73,10 @@ typedef struct pf_opts {
   int32_t factor_max_levels;  /* at most this many sparse elimination levels before the dense
                                  core; the set-up picks the cheapest split, default 8 */
   int32_t factor_max_core;    /* largest dense Schur core, default 384 */
+  /* feeder solve */
+  int32_t zbus_sparse;        /* 0: dense product Z r on the matrix cores (default); 1: Y_NN^-1 r
+                                 by level-scheduled solves with a sparse L D L^T of Y_NN (the
+                                 sparse variant named as future work in Sec. II-B) */
 } pf_opts;
 
 void pf_opts_default(pf_opts* out);

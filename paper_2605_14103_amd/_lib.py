@@ -32,6 +32,7 @@ class PfOpts(ctypes.Structure):
         ("precond_block", c_int32),
         ("factor_max_levels", c_int32),
         ("factor_max_core", c_int32),
+        ("zbus_sparse", c_int32),
     ]
 
 

@@ -74,6 +74,7 @@ pf_opts resolve_opts(const pf_opts* o) {
   require(r.precond_block >= 0, "precond_block must be >= 0");
   require(r.factor_max_levels >= 1, "factor_max_levels must be >= 1");
   require(r.factor_max_core >= 0 && r.factor_max_core <= 2048, "factor_max_core must be 0..2048");
+  require(r.zbus_sparse == 0 || r.zbus_sparse == 1, "zbus_sparse must be 0 or 1");
   return r;
 }
 
@@ -119,6 +120,7 @@ void pf_opts_default(pf_opts* o) {
   o->precond_block = 0;
   o->factor_max_levels = 8;
   o->factor_max_core = 384;
+  o->zbus_sparse = 0;
 }
 
 const char* pf_last_error(void) { return g_last_error.c_str(); }

@@ -168,6 +168,7 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     a.sum_abs_change = sum_abs_change;
     a.tol = o.tol;
     a.max_iter = o.zbus_max_iter;
+    a.sparse = o.zbus_sparse;
     a.v = net->ws_v.as<double>();
     a.r = net->ws_r.as<void>();
     a.st = net->ws_s.as<double>();

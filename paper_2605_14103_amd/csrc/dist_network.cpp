@@ -7,6 +7,7 @@
 #include <string>
 
 #include "dist.hpp"
+#include "zfactor.hpp"
 
 namespace pfx {
 
@@ -83,6 +84,25 @@ DistDev DistNetwork::view() const {
   d.c = c.as<double2>();
   d.v0 = v0.as<double>();
   d.free2ext = free2ext_d.as<int>();
+  d.zf_nf = zf_nf;
+  d.zf_nb = zf_nb;
+  d.zf_perm = zf_perm.as<int>();
+  d.zf_flev = zf_flev.as<int>();
+  d.zf_blev = zf_blev.as<int>();
+  d.zf_foff = zf_foff.as<int>();
+  d.zf_fwid = zf_fwid.as<int>();
+  d.zf_frow = zf_frow.as<int>();
+  d.zf_fcol = zf_fcol.as<int>();
+  d.zf_boff = zf_boff.as<int>();
+  d.zf_bwid = zf_bwid.as<int>();
+  d.zf_brow = zf_brow.as<int>();
+  d.zf_bcol = zf_bcol.as<int>();
+  d.zf_fval64 = zf_fval64.as<double2>();
+  d.zf_bval64 = zf_bval64.as<double2>();
+  d.zf_bd64 = zf_bd64.as<double2>();
+  d.zf_fval32 = zf_fval32.as<float2>();
+  d.zf_bval32 = zf_bval32.as<float2>();
+  d.zf_bd32 = zf_bd32.as<float2>();
   return d;
 }
 
@@ -155,7 +175,33 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
   }
   net->nnz = nnz_nn;
 
+  // Sparse L D L^T of Y_NN for the sparse variant, checked against the dense
+  // inverse below.
+  std::vector<int> zp(nN + 1, 0), zc;
+  std::vector<cplx> zv;
+  for (int i = 0; i < nN; ++i) {
+    for (auto [j, re, im] : rows[i]) {
+      zc.push_back(j);
+      zv.push_back(cplx(re, im));
+    }
+    zp[i + 1] = (int)zc.size();
+  }
+  const ComplexLdl zf = complex_ldl(nN, zp, zc, zv);
   invert_dense(Yd, nN);  // Yd now holds Z
+  {
+    std::vector<cplx> b(nN), ref(nN, cplx(0.0));
+    for (int i = 0; i < nN; ++i) b[i] = cplx(std::sin(0.37 * i + 0.1), std::cos(0.91 * i));
+    for (int i = 0; i < nN; ++i)
+      for (int l = 0; l < nN; ++l) ref[i] += Yd[(size_t)i * nN + l] * b[l];
+    const std::vector<cplx> x = complex_ldl_solve(zf, b);
+    double err = 0.0, mag = 0.0;
+    for (int i = 0; i < nN; ++i) {
+      err = std::max(err, std::abs(x[i] - ref[i]));
+      mag = std::max(mag, std::abs(ref[i]));
+    }
+    if (!(err <= 1e-8 * mag))
+      fail(PF_SINGULAR_SETUP, "sparse factor of Y_NN disagrees with the dense inverse (" + std::to_string(err) + ")");
+  }
   std::vector<double> v0(2 * (size_t)nN);
   for (int i = 0; i < nN; ++i) {
     cplx s(0.0);
@@ -209,6 +255,85 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
   for (int i = nN; i < nNs; ++i) nodes[4 * i + 1] = -1;
 
   upload_sell(ctx, build_sell(rows, 4), true, net->y);
+  {
+    // Level slices of the two solves (see DistDev): rows of each level in
+    // chunks of 64, entries padded to a multiple of 4.
+    struct Slices {
+      std::vector<int> lev, off, wid, row, col;
+      std::vector<cplx> val, dinv;
+    };
+    auto slices = [&](const std::vector<int>& lev_start, const std::vector<int>& lev_rows,
+                      const std::vector<int>& rptr, const std::vector<int>& rcol, const std::vector<cplx>& rval,
+                      bool with_dinv) {
+      Slices S;
+      const int nl = (int)lev_start.size() - 1;
+      S.lev.push_back(0);
+      for (int l = 0; l < nl; ++l) {
+        for (int q0 = lev_start[l]; q0 < lev_start[l + 1]; q0 += 64) {
+          const int q1 = std::min(q0 + 64, lev_start[l + 1]);
+          int w = 0;
+          for (int q = q0; q < q1; ++q) w = std::max(w, rptr[lev_rows[q] + 1] - rptr[lev_rows[q]]);
+          w = (w + 3) / 4 * 4;
+          S.off.push_back((int)S.col.size());
+          S.wid.push_back(w);
+          const size_t base = S.col.size();
+          S.col.resize(base + 64 * (size_t)w, 0);
+          S.val.resize(base + 64 * (size_t)w, cplx(0.0));
+          for (int lane = 0; lane < 64; ++lane) {
+            const int q = q0 + lane;
+            const int r = q < q1 ? lev_rows[q] : -1;
+            S.row.push_back(r);
+            if (with_dinv) S.dinv.push_back(r >= 0 ? zf.dinv[r] : cplx(0.0));
+            if (r < 0) continue;
+            for (int t = rptr[r], e = 0; t < rptr[r + 1]; ++t, ++e) {
+              S.col[base + 64 * (size_t)e + lane] = rcol[t];
+              S.val[base + 64 * (size_t)e + lane] = rval[t];
+            }
+          }
+        }
+        S.lev.push_back((int)S.wid.size());
+      }
+      if (S.col.empty()) {
+        S.col.push_back(0);
+        S.val.push_back(cplx(0.0));
+      }
+      return S;
+    };
+    const Slices F = slices(zf.f_lev, zf.f_rows, zf.L_ptr, zf.L_col, zf.L_val, false);
+    const Slices Bk = slices(zf.b_lev, zf.b_rows, zf.T_ptr, zf.T_col, zf.T_val, true);
+    auto interleave = [](const std::vector<cplx>& v) {
+      std::vector<double> d(2 * v.size());
+      for (size_t i = 0; i < v.size(); ++i) {
+        d[2 * i] = v[i].real();
+        d[2 * i + 1] = v[i].imag();
+      }
+      return d;
+    };
+    auto up64 = [&](const std::vector<cplx>& v) { return upload(ctx, interleave(v)); };
+    auto up32 = [&](const std::vector<cplx>& v) {
+      const std::vector<double> d = interleave(v);
+      return upload(ctx, std::vector<float>(d.begin(), d.end()));
+    };
+    net->zf_nf = (int)zf.f_lev.size() - 1;
+    net->zf_nb = (int)zf.b_lev.size() - 1;
+    net->zf_perm = upload(ctx, zf.perm);
+    net->zf_flev = upload(ctx, F.lev);
+    net->zf_blev = upload(ctx, Bk.lev);
+    net->zf_foff = upload(ctx, F.off.empty() ? std::vector<int>{0} : F.off);
+    net->zf_fwid = upload(ctx, F.wid.empty() ? std::vector<int>{0} : F.wid);
+    net->zf_frow = upload(ctx, F.row.empty() ? std::vector<int>{-1} : F.row);
+    net->zf_fcol = upload(ctx, F.col);
+    net->zf_boff = upload(ctx, Bk.off.empty() ? std::vector<int>{0} : Bk.off);
+    net->zf_bwid = upload(ctx, Bk.wid.empty() ? std::vector<int>{0} : Bk.wid);
+    net->zf_brow = upload(ctx, Bk.row.empty() ? std::vector<int>{-1} : Bk.row);
+    net->zf_bcol = upload(ctx, Bk.col);
+    net->zf_fval64 = up64(F.val);
+    net->zf_bval64 = up64(Bk.val);
+    net->zf_bd64 = up64(Bk.dinv.empty() ? std::vector<cplx>{cplx(0.0)} : Bk.dinv);
+    net->zf_fval32 = up32(F.val);
+    net->zf_bval32 = up32(Bk.val);
+    net->zf_bd32 = up32(Bk.dinv.empty() ? std::vector<cplx>{cplx(0.0)} : Bk.dinv);
+  }
   net->node = upload(ctx, nodes);
   net->c = upload(ctx, cc);
   net->v0 = upload(ctx, v0);

@@ -337,6 +337,7 @@ void Engine::run_job(Worker& wk, const Job& job) {
     a.sum_abs_change = nullptr;
     a.tol = opts.tol;
     a.max_iter = opts.zbus_max_iter;
+    a.sparse = opts.zbus_sparse;
     a.v = ws_d.as<double>() + (size_t)first * net.Kp;
     a.r = wk.r.as<void>();
     a.st = st_d.as<double>() + (size_t)first * 3;

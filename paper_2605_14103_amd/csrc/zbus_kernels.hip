@@ -14,6 +14,8 @@
 //                 max |v * conj(r)|, flags, sum |v|
 //   zb_gemm       D = R W (real-block form of Z r) on MFMA 16x16x4 tiles, with
 //                 the FP64 update v += D fused into the epilogue
+//   zb_sparse     (sparse variant, instead of zb_gemm) v += Y_NN^-1 r by
+//                 level-scheduled solves with the sparse L D L^T of Y_NN
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -337,6 +339,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   }
 }
 
+// Sparse variant of the update: v += Y_NN^-1 r by the L D L^T factor of
+// Y_NN (zfactor.hpp), one wavefront per active scenario.  r is gathered into
+// factor order in LDS; the forward solve L z = r and the backward solve
+// L^T x = D^-1 z run level by level, in place: a level's rows are
+// independent (a row reads only rows of earlier levels) and sit one per lane
+// in 64-row slices whose entries are loaded together (rounds of four), so a
+// level costs one round of loads.  x is added to v in FP64.  Arithmetic in T
+// (FP32 in mixed mode, the FP64 residual then refines the result as for the
+// dense product).
+template <typename T>
+__global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a) {
+  using T2 = typename Vec2<T>::type;
+  extern __shared__ __align__(16) unsigned char zsm[];
+  T2* u = reinterpret_cast<T2*>(zsm);  // [nN]
+  const int b = blockIdx.x;
+  if (a.active[b] == 0) return;
+  const int nN = net.nN, lane = threadIdx.x;
+  const T* r = reinterpret_cast<const T*>(a.r) + (int64_t)b * net.Kp;
+  constexpr bool f64 = sizeof(T) == 8;
+  const T2* FV = f64 ? reinterpret_cast<const T2*>(net.zf_fval64) : reinterpret_cast<const T2*>(net.zf_fval32);
+  const T2* BV = f64 ? reinterpret_cast<const T2*>(net.zf_bval64) : reinterpret_cast<const T2*>(net.zf_bval32);
+  const T2* BD = f64 ? reinterpret_cast<const T2*>(net.zf_bd64) : reinterpret_cast<const T2*>(net.zf_bd32);
+  for (int p = lane; p < nN; p += WAVE) {
+    const int i = cld(net.zf_perm, (unsigned)p);
+    T2 x;
+    x.x = r[2 * i];
+    x.y = r[2 * i + 1];
+    u[p] = x;
+  }
+  __syncthreads();
+  // acc -= sum over the slice row's entries of value * u[column]
+  auto row_dot = [&](const T2* val, const int* col, int off, int wd, T2& acc) {
+    for (int e = 0; e < wd; e += 4) {
+      T2 c[4];
+      int j[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned q = (unsigned)(off + (e + t) * WAVE + lane);
+        c[t] = cld(val, q);
+        j[t] = cld(col, q);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const T2 z = u[j[t]];
+        acc.x -= c[t].x * z.x - c[t].y * z.y;
+        acc.y -= c[t].x * z.y + c[t].y * z.x;
+      }
+    }
+  };
+  // forward: z_i = r_i - sum_j L_ij z_j
+  for (int l = 0; l < net.zf_nf; ++l) {
+    const int q1 = cld(net.zf_flev, (unsigned)(l + 1));
+    for (int q = cld(net.zf_flev, (unsigned)l); q < q1; ++q) {
+      const int i = cld(net.zf_frow, (unsigned)(q * WAVE + lane));
+      const int off = cld(net.zf_foff, (unsigned)q), wd = cld(net.zf_fwid, (unsigned)q);
+      T2 acc = u[i < 0 ? 0 : i];
+      row_dot(FV, net.zf_fcol, off, wd, acc);
+      if (i >= 0) u[i] = acc;
+    }
+    __syncthreads();
+  }
+  // backward: x_j = z_j / D_j - sum_i L_ij x_i (i > j)
+  for (int l = 0; l < net.zf_nb; ++l) {
+    const int q1 = cld(net.zf_blev, (unsigned)(l + 1));
+    for (int q = cld(net.zf_blev, (unsigned)l); q < q1; ++q) {
+      const int j = cld(net.zf_brow, (unsigned)(q * WAVE + lane));
+      const int off = cld(net.zf_boff, (unsigned)q), wd = cld(net.zf_bwid, (unsigned)q);
+      const T2 d = cld(BD, (unsigned)(q * WAVE + lane));
+      const T2 z = u[j < 0 ? 0 : j];
+      T2 acc;
+      acc.x = z.x * d.x - z.y * d.y;
+      acc.y = z.x * d.y + z.y * d.x;
+      row_dot(BV, net.zf_bcol, off, wd, acc);
+      if (j >= 0) u[j] = acc;
+    }
+    __syncthreads();
+  }
+  double* v = a.v + (int64_t)b * net.Kp;
+  for (int p = lane; p < nN; p += WAVE) {
+    const int i = cld(net.zf_perm, (unsigned)p);
+    const T2 x = u[p];
+    v[2 * i] += (double)x.x;
+    v[2 * i + 1] += (double)x.y;
+  }
+}
+
 __global__ __launch_bounds__(ZB_THREADS) void zb_finish(DistDev net, ZbusLaunch a, const int* slack,
                                                        const double* vslack) {
   const int b = blockIdx.x;
@@ -390,7 +478,11 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
         if (a.count_host[it - 1] == 0) break;
       }
       if (it == a.max_iter) break;
-      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
+      if (a.sparse) {
+        hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a);
+      } else {
+        hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
+      }
       PFX_HIP(hipGetLastError());
     }
   } catch (...) {

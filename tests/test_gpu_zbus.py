@@ -121,3 +121,28 @@ def test_large_feeder_many_slots(ctx):
         res = _solve(net, batch, precision=pf.precision(precision))
         _check(fd, batch, res, np.arange(batch.batch), f"feeder700 {precision}")
     net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sparse_variant(ctx, precision):
+    """The sparse variant (Y_NN^-1 r by the L D L^T of Y_NN instead of the dense
+    Z product) against the oracle: a small feeder in full, the 300-bus feeder
+    at its full batch (sampled) and the 700-bus feeder."""
+    from paper_2605_14103_amd import pf
+    cases = [(fdm.FeederConfig("feeder40s", n_bus=40, max_depth=25, batch=33, seed=43), None),
+             (fdm.FEEDER300, np.array([0, 1, 2047, 4095])),
+             (fdm.FeederConfig("feeder700s", n_bus=700, max_depth=30, batch=5, seed=701), None)]
+    for cfg, cols in cases:
+        fd = fdm.make_feeder(cfg)
+        batch = fdm.make_batch(fd, cfg)
+        net = pf.DistNetwork.from_feeder(ctx, fd)
+        res = _solve(net, batch, precision=pf.precision(precision), zbus_sparse=1)
+        assert res.converged.cpu().numpy().all()
+        assert res.mismatch.cpu().numpy().max() <= 1e-8
+        _check(fd, batch, res, np.arange(batch.batch) if cols is None else cols,
+               f"{cfg.name} sparse {precision}")
+        dense = _solve(net, batch, precision=pf.precision(precision))
+        dv = np.abs(res.v.cpu().numpy() - dense.v.cpu().numpy()).max()
+        say(f"{cfg.name} sparse vs dense {precision}: max |dv| {dv:.2e}")
+        assert dv <= 2e-6
+        net.close()
