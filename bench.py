@@ -266,6 +266,45 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
     return line
 
 
+def bench_feeder_sizes(steps: int, warmup: int) -> dict:
+    """Dense Z product against the sparse Y_NN factor as the feeder grows (batch 1024, both precisions)."""
+    import torch
+
+    from paper_2605_14103_amd import pf
+    from workloads import feeder as fdm
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rows = []
+    ctx = pf.Context(0)
+    for n_bus in (100, 300, 600, 908):
+        cfg = fdm.FeederConfig(f"feeder{n_bus}", n_bus=n_bus, max_depth=25, batch=1024, seed=n_bus)
+        fd = fdm.make_feeder(cfg)
+        batch = fdm.make_batch(fd, cfg)
+        t0 = time.perf_counter()
+        net = pf.DistNetwork.from_feeder(ctx, fd)
+        setup_s = time.perf_counter() - t0
+        sw, sd = dev(batch.s_wye), dev(batch.s_delta)
+        for sparse in (0, 1):
+            for prec in ("fp64", "mixed"):
+                ms, _, out = time_steps(
+                    lambda: net.solve(sw, sd, precision=pf.precision(prec), zbus_sparse=sparse), steps, warmup)
+                conv = int(out.converged.sum().item())
+                rows.append({"workload": cfg.name, "free_nodes": net.info["n_free"], "batch": cfg.batch,
+                             "update": "sparse" if sparse else "dense", "precision": prec,
+                             "ms": float(ms.mean()), "solves_per_s": conv / (float(ms.mean()) * 1e-3),
+                             "converged": conv, "iters_mean": float(out.iters.double().mean().item()),
+                             "setup_s": setup_s})
+                print(f"[sizes] {cfg.name} nN={net.info['n_free']} {rows[-1]['update']} {prec} "
+                      f"{ms.mean():.3f} ms", file=sys.stderr, flush=True)
+        net.close()
+    ctx.close()
+    best = max(r["solves_per_s"] for r in rows if r["workload"] == "feeder300" and r["precision"] == "fp64")
+    return {"metric": METRIC, "value": best, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "feeder size sweep: 100-908 buses, batch 1024, dense Z against sparse Y_NN"},
+            "sizes": rows}
+
+
 def bench_adjoint(steps: int, warmup: int) -> dict:
     """Branch-loss gradient w.r.t. PQ injections (adjoint GMRES) on the 2000-bus grid, batch 256."""
     import torch
@@ -428,10 +467,11 @@ def counters_run(workload: str) -> dict:
         batch = fdm.make_batch(fd, fdm.FEEDER300)
         net = pf.DistNetwork.from_feeder(ctx, fd)
         sw, sd = dev(batch.s_wye), dev(batch.s_delta)
-        for prec in ("fp64", "mixed"):
-            res = net.solve(sw, sd, precision=pf.precision(prec))
-            torch.cuda.synchronize()
-            out[prec] = {"iters": res.iters.cpu().numpy().tolist()[:4]}
+        for sparse in (0, 1):
+            for prec in ("fp64", "mixed"):
+                res = net.solve(sw, sd, precision=pf.precision(prec), zbus_sparse=sparse)
+                torch.cuda.synchronize()
+                out[prec + ("_sparse" if sparse else "")] = {"iters": res.iters.cpu().numpy().tolist()[:4]}
     else:
         from workloads import transmission as tx
         cfg = {"tx2000": tx.TX2000, "tx30": tx.TX30}[workload]
@@ -454,7 +494,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tx2000",
-                    choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep"])
+                    choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep", "feeder_sizes"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--streams", default="1,2,1",
@@ -484,6 +524,8 @@ def main() -> int:
         line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")))
     elif a.workload == "sweep":
         line = bench_sweep(a.steps, a.warmup)
+    elif a.workload == "feeder_sizes":
+        line = bench_feeder_sizes(a.steps, a.warmup)
     else:
         line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
     print(json.dumps(line), flush=True)

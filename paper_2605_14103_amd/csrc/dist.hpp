@@ -31,28 +31,25 @@ struct DistDev {
   const double2* c;        // [nNs] Y_NS v_S (zero past nN)
   const double* v0;        // no-load voltage, complex interleaved [nN]
   const int* free2ext;     // free node -> caller's node index
-  // Sparse L D L^T of Y_NN (zfactor.hpp) for the sparse variant, factor
-  // position p holding free node perm[p].  Each solve is laid out level by
-  // level in slices of 64 rows (one row per lane): slice q holds row ids
+  // Sparse L D L^T of Y_NN (zfactor.hpp) for the sparse variant; free node
+  // i sits at factor position pinv[i].  Each solve is a list of slices of
+  // 64 rows (one row per lane), level after level: slice q holds row ids
   // row[64 q + lane] (-1 for padding) and entries (value, column) at
-  // off[q] + 64 e + lane for e < width[q] (a multiple of 4, padding zero);
-  // level l owns slices lev[l] .. lev[l + 1).  The backward slices also hold
-  // each row's 1 / D.  Values complex, in FP64 and FP32.
-  int zf_nf, zf_nb;
-  const int* zf_perm;
-  const int* zf_flev;    // [nf + 1]
-  const int* zf_blev;    // [nb + 1]
-  const int* zf_foff;    // per forward slice
-  const int* zf_fwid;
+  // meta[q].x + 64 e + lane for e < meta[q].y (a multiple of 4, at least 4,
+  // padding zero); meta[q].z is 1 on the last slice of a level.  The
+  // backward slices also hold each row's 1 / D.  Values complex, in FP64
+  // and FP32.
+  int zf_nfq, zf_nbq;          // forward / backward slice counts
+  const int* zf_pinv;          // [nN]
+  const int4* zf_fmeta;
   const int* zf_frow;
   const int* zf_fcol;
-  const int* zf_boff;    // per backward slice
-  const int* zf_bwid;
+  const int4* zf_bmeta;
   const int* zf_brow;
   const int* zf_bcol;
   const double2* zf_fval64;
   const double2* zf_bval64;
-  const double2* zf_bd64;   // [64 x backward slices] 1 / D of the slice's rows
+  const double2* zf_bd64;      // [64 x backward slices]
   const float2* zf_fval32;
   const float2* zf_bval32;
   const float2* zf_bd32;
@@ -66,8 +63,8 @@ struct DistNetwork {
   std::vector<int> free2ext;
   SellBuffers y;
   DeviceBuffer node, c, v0, free2ext_d;
-  int zf_nf = 0, zf_nb = 0;
-  DeviceBuffer zf_perm, zf_flev, zf_blev, zf_foff, zf_fwid, zf_frow, zf_fcol, zf_boff, zf_bwid, zf_brow, zf_bcol;
+  int zf_nfq = 0, zf_nbq = 0;
+  DeviceBuffer zf_pinv, zf_fmeta, zf_frow, zf_fcol, zf_bmeta, zf_brow, zf_bcol;
   DeviceBuffer zf_fval64, zf_bval64, zf_bd64, zf_fval32, zf_bval32, zf_bd32;
   DeviceBuffer W64, W32;   // Kp x Np real-block Z (Np = 2 nN rounded up to the N tile)
   DeviceBuffer slack_d;    // 3 slack node indices

@@ -84,17 +84,13 @@ DistDev DistNetwork::view() const {
   d.c = c.as<double2>();
   d.v0 = v0.as<double>();
   d.free2ext = free2ext_d.as<int>();
-  d.zf_nf = zf_nf;
-  d.zf_nb = zf_nb;
-  d.zf_perm = zf_perm.as<int>();
-  d.zf_flev = zf_flev.as<int>();
-  d.zf_blev = zf_blev.as<int>();
-  d.zf_foff = zf_foff.as<int>();
-  d.zf_fwid = zf_fwid.as<int>();
+  d.zf_nfq = zf_nfq;
+  d.zf_nbq = zf_nbq;
+  d.zf_pinv = zf_pinv.as<int>();
+  d.zf_fmeta = zf_fmeta.as<int4>();
   d.zf_frow = zf_frow.as<int>();
   d.zf_fcol = zf_fcol.as<int>();
-  d.zf_boff = zf_boff.as<int>();
-  d.zf_bwid = zf_bwid.as<int>();
+  d.zf_bmeta = zf_bmeta.as<int4>();
   d.zf_brow = zf_brow.as<int>();
   d.zf_bcol = zf_bcol.as<int>();
   d.zf_fval64 = zf_fval64.as<double2>();
@@ -259,24 +255,24 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
     // Level slices of the two solves (see DistDev): rows of each level in
     // chunks of 64, entries padded to a multiple of 4.
     struct Slices {
-      std::vector<int> lev, off, wid, row, col;
+      std::vector<int> meta, row, col;
       std::vector<cplx> val, dinv;
+      int count = 0;
     };
     auto slices = [&](const std::vector<int>& lev_start, const std::vector<int>& lev_rows,
                       const std::vector<int>& rptr, const std::vector<int>& rcol, const std::vector<cplx>& rval,
                       bool with_dinv) {
       Slices S;
       const int nl = (int)lev_start.size() - 1;
-      S.lev.push_back(0);
       for (int l = 0; l < nl; ++l) {
         for (int q0 = lev_start[l]; q0 < lev_start[l + 1]; q0 += 64) {
           const int q1 = std::min(q0 + 64, lev_start[l + 1]);
-          int w = 0;
+          int w = 4;
           for (int q = q0; q < q1; ++q) w = std::max(w, rptr[lev_rows[q] + 1] - rptr[lev_rows[q]]);
           w = (w + 3) / 4 * 4;
-          S.off.push_back((int)S.col.size());
-          S.wid.push_back(w);
           const size_t base = S.col.size();
+          S.meta.insert(S.meta.end(), {(int)base, w, q1 == lev_start[l + 1] ? 1 : 0, 0});
+          ++S.count;
           S.col.resize(base + 64 * (size_t)w, 0);
           S.val.resize(base + 64 * (size_t)w, cplx(0.0));
           for (int lane = 0; lane < 64; ++lane) {
@@ -291,11 +287,13 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
             }
           }
         }
-        S.lev.push_back((int)S.wid.size());
       }
-      if (S.col.empty()) {
-        S.col.push_back(0);
-        S.val.push_back(cplx(0.0));
+      if (S.count == 0) {  // keep every buffer non-empty
+        S.meta = {0, 0, 0, 0};
+        S.row = {-1};
+        S.col = {0};
+        S.val = {cplx(0.0)};
+        S.dinv = {cplx(0.0)};
       }
       return S;
     };
@@ -314,25 +312,23 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
       const std::vector<double> d = interleave(v);
       return upload(ctx, std::vector<float>(d.begin(), d.end()));
     };
-    net->zf_nf = (int)zf.f_lev.size() - 1;
-    net->zf_nb = (int)zf.b_lev.size() - 1;
-    net->zf_perm = upload(ctx, zf.perm);
-    net->zf_flev = upload(ctx, F.lev);
-    net->zf_blev = upload(ctx, Bk.lev);
-    net->zf_foff = upload(ctx, F.off.empty() ? std::vector<int>{0} : F.off);
-    net->zf_fwid = upload(ctx, F.wid.empty() ? std::vector<int>{0} : F.wid);
-    net->zf_frow = upload(ctx, F.row.empty() ? std::vector<int>{-1} : F.row);
+    std::vector<int> pinv(nN > 0 ? nN : 1, 0);
+    for (int p = 0; p < nN; ++p) pinv[zf.perm[p]] = p;
+    net->zf_nfq = F.count;
+    net->zf_nbq = Bk.count;
+    net->zf_pinv = upload(ctx, pinv);
+    net->zf_fmeta = upload(ctx, F.meta);
+    net->zf_frow = upload(ctx, F.row);
     net->zf_fcol = upload(ctx, F.col);
-    net->zf_boff = upload(ctx, Bk.off.empty() ? std::vector<int>{0} : Bk.off);
-    net->zf_bwid = upload(ctx, Bk.wid.empty() ? std::vector<int>{0} : Bk.wid);
-    net->zf_brow = upload(ctx, Bk.row.empty() ? std::vector<int>{-1} : Bk.row);
+    net->zf_bmeta = upload(ctx, Bk.meta);
+    net->zf_brow = upload(ctx, Bk.row);
     net->zf_bcol = upload(ctx, Bk.col);
     net->zf_fval64 = up64(F.val);
     net->zf_bval64 = up64(Bk.val);
-    net->zf_bd64 = up64(Bk.dinv.empty() ? std::vector<cplx>{cplx(0.0)} : Bk.dinv);
+    net->zf_bd64 = up64(Bk.dinv);
     net->zf_fval32 = up32(F.val);
     net->zf_bval32 = up32(Bk.val);
-    net->zf_bd32 = up32(Bk.dinv.empty() ? std::vector<cplx>{cplx(0.0)} : Bk.dinv);
+    net->zf_bd32 = up32(Bk.dinv);
   }
   net->node = upload(ctx, nodes);
   net->c = upload(ctx, cc);

@@ -339,13 +339,80 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   }
 }
 
+// One triangular solve of the sparse variant, in place on u (LDS, factor
+// order).  Slices run in order with a barrier after each level's last slice:
+// a level's rows read only rows of earlier levels, so its slices need no
+// barrier between them.  The next slice's descriptor, row ids, first round of
+// entries (and 1 / D) are loaded while the current slice computes, so a
+// level's cost is its LDS gathers and barrier rather than a chain of
+// dependent loads.  BACK: u_i <- u_i / D_i - sum L^T_ij u_j (with the row's
+// 1 / D); otherwise u_i <- u_i - sum L_ij u_j.
+template <typename T, bool BACK>
+__device__ __forceinline__ void zf_solve(typename Vec2<T>::type* u, int nq, const int4* meta, const int* row,
+                                         const int* col, const typename Vec2<T>::type* val,
+                                         const typename Vec2<T>::type* dinv) {
+  using T2 = typename Vec2<T>::type;
+  if (nq == 0) return;
+  const int lane = threadIdx.x;
+  auto round = [&](int at, T2 (&c)[4], int (&j)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      c[t] = cld(val, (unsigned)(at + t * WAVE + lane));
+      j[t] = cld(col, (unsigned)(at + t * WAVE + lane));
+    }
+  };
+  auto apply = [&](const T2 (&c)[4], const int (&j)[4], T2& acc) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const T2 z = u[j[t]];
+      acc.x -= c[t].x * z.x - c[t].y * z.y;
+      acc.y -= c[t].x * z.y + c[t].y * z.x;
+    }
+  };
+  int4 m = cld(meta, 0u);
+  int i = cld(row, (unsigned)lane);
+  T2 c[4], d;
+  int j[4];
+  round(m.x, c, j);
+  if (BACK) d = cld(dinv, (unsigned)lane);
+  for (int q = 0; q < nq; ++q) {
+    const int qn = q + 1 < nq ? q + 1 : q;  // the last slice re-reads itself
+    const int4 mn = cld(meta, (unsigned)qn);
+    const int in = cld(row, (unsigned)(qn * WAVE + lane));
+    T2 cn[4], dn;
+    int jn[4];
+    round(mn.x, cn, jn);
+    if (BACK) dn = cld(dinv, (unsigned)(qn * WAVE + lane));
+    const T2 z = u[i < 0 ? 0 : i];
+    T2 acc = z;
+    if (BACK) {
+      acc.x = z.x * d.x - z.y * d.y;
+      acc.y = z.x * d.y + z.y * d.x;
+    }
+    apply(c, j, acc);
+    for (int e = 4; e < m.y; e += 4) {
+      T2 c2[4];
+      int j2[4];
+      round(m.x + e * WAVE, c2, j2);
+      apply(c2, j2, acc);
+    }
+    if (i >= 0) u[i] = acc;
+    if (m.z) __syncthreads();
+    m = mn;
+    i = in;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      c[t] = cn[t];
+      j[t] = jn[t];
+    }
+    if (BACK) d = dn;
+  }
+}
+
 // Sparse variant of the update: v += Y_NN^-1 r by the L D L^T factor of
-// Y_NN (zfactor.hpp), one wavefront per active scenario.  r is gathered into
-// factor order in LDS; the forward solve L z = r and the backward solve
-// L^T x = D^-1 z run level by level, in place: a level's rows are
-// independent (a row reads only rows of earlier levels) and sit one per lane
-// in 64-row slices whose entries are loaded together (rounds of four), so a
-// level costs one round of loads.  x is added to v in FP64.  Arithmetic in T
+// Y_NN (zfactor.hpp), one wavefront per active scenario: r is placed into
+// factor order in LDS, the forward solve L z = r and the backward solve
+// L^T x = D^-1 z run in place, and x is added to v in FP64.  Arithmetic in T
 // (FP32 in mixed mode, the FP64 residual then refines the result as for the
 // dense product).
 template <typename T>
@@ -356,72 +423,23 @@ __global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a) {
   const int b = blockIdx.x;
   if (a.active[b] == 0) return;
   const int nN = net.nN, lane = threadIdx.x;
-  const T* r = reinterpret_cast<const T*>(a.r) + (int64_t)b * net.Kp;
+  const T2* r = reinterpret_cast<const T2*>(reinterpret_cast<const T*>(a.r) + (int64_t)b * net.Kp);
   constexpr bool f64 = sizeof(T) == 8;
-  const T2* FV = f64 ? reinterpret_cast<const T2*>(net.zf_fval64) : reinterpret_cast<const T2*>(net.zf_fval32);
-  const T2* BV = f64 ? reinterpret_cast<const T2*>(net.zf_bval64) : reinterpret_cast<const T2*>(net.zf_bval32);
-  const T2* BD = f64 ? reinterpret_cast<const T2*>(net.zf_bd64) : reinterpret_cast<const T2*>(net.zf_bd32);
-  for (int p = lane; p < nN; p += WAVE) {
-    const int i = cld(net.zf_perm, (unsigned)p);
-    T2 x;
-    x.x = r[2 * i];
-    x.y = r[2 * i + 1];
-    u[p] = x;
-  }
+  for (int i = lane; i < nN; i += WAVE) u[cld(net.zf_pinv, (unsigned)i)] = r[i];
   __syncthreads();
-  // acc -= sum over the slice row's entries of value * u[column]
-  auto row_dot = [&](const T2* val, const int* col, int off, int wd, T2& acc) {
-    for (int e = 0; e < wd; e += 4) {
-      T2 c[4];
-      int j[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const unsigned q = (unsigned)(off + (e + t) * WAVE + lane);
-        c[t] = cld(val, q);
-        j[t] = cld(col, q);
-      }
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const T2 z = u[j[t]];
-        acc.x -= c[t].x * z.x - c[t].y * z.y;
-        acc.y -= c[t].x * z.y + c[t].y * z.x;
-      }
-    }
-  };
-  // forward: z_i = r_i - sum_j L_ij z_j
-  for (int l = 0; l < net.zf_nf; ++l) {
-    const int q1 = cld(net.zf_flev, (unsigned)(l + 1));
-    for (int q = cld(net.zf_flev, (unsigned)l); q < q1; ++q) {
-      const int i = cld(net.zf_frow, (unsigned)(q * WAVE + lane));
-      const int off = cld(net.zf_foff, (unsigned)q), wd = cld(net.zf_fwid, (unsigned)q);
-      T2 acc = u[i < 0 ? 0 : i];
-      row_dot(FV, net.zf_fcol, off, wd, acc);
-      if (i >= 0) u[i] = acc;
-    }
-    __syncthreads();
-  }
-  // backward: x_j = z_j / D_j - sum_i L_ij x_i (i > j)
-  for (int l = 0; l < net.zf_nb; ++l) {
-    const int q1 = cld(net.zf_blev, (unsigned)(l + 1));
-    for (int q = cld(net.zf_blev, (unsigned)l); q < q1; ++q) {
-      const int j = cld(net.zf_brow, (unsigned)(q * WAVE + lane));
-      const int off = cld(net.zf_boff, (unsigned)q), wd = cld(net.zf_bwid, (unsigned)q);
-      const T2 d = cld(BD, (unsigned)(q * WAVE + lane));
-      const T2 z = u[j < 0 ? 0 : j];
-      T2 acc;
-      acc.x = z.x * d.x - z.y * d.y;
-      acc.y = z.x * d.y + z.y * d.x;
-      row_dot(BV, net.zf_bcol, off, wd, acc);
-      if (j >= 0) u[j] = acc;
-    }
-    __syncthreads();
-  }
-  double* v = a.v + (int64_t)b * net.Kp;
-  for (int p = lane; p < nN; p += WAVE) {
-    const int i = cld(net.zf_perm, (unsigned)p);
-    const T2 x = u[p];
-    v[2 * i] += (double)x.x;
-    v[2 * i + 1] += (double)x.y;
+  zf_solve<T, false>(u, net.zf_nfq, net.zf_fmeta, net.zf_frow, net.zf_fcol,
+                     f64 ? reinterpret_cast<const T2*>(net.zf_fval64) : reinterpret_cast<const T2*>(net.zf_fval32),
+                     nullptr);
+  zf_solve<T, true>(u, net.zf_nbq, net.zf_bmeta, net.zf_brow, net.zf_bcol,
+                    f64 ? reinterpret_cast<const T2*>(net.zf_bval64) : reinterpret_cast<const T2*>(net.zf_bval32),
+                    f64 ? reinterpret_cast<const T2*>(net.zf_bd64) : reinterpret_cast<const T2*>(net.zf_bd32));
+  double2* v = reinterpret_cast<double2*>(a.v + (int64_t)b * net.Kp);
+  for (int i = lane; i < nN; i += WAVE) {
+    const T2 x = u[cld(net.zf_pinv, (unsigned)i)];
+    double2 y = v[i];
+    y.x += (double)x.x;
+    y.y += (double)x.y;
+    v[i] = y;
   }
 }
 
