@@ -266,6 +266,53 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
     return line
 
 
+def bench_tx_switch(steps: int, warmup: int) -> dict:
+    """Topology-action batch on the 2000-bus grid: batch 1024, every scenario
+    with one branch out of service (its own Ybus values on the shared pattern),
+    against the same loads with the network's own values."""
+    import torch
+
+    from paper_2605_14103_amd import pf
+    from workloads import transmission as tx
+    cfg = tx.TX2000
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg)
+    on = tx.make_outages(grid, batch.batch, n_out=1, seed=cfg.seed + 7)
+    ctx = pf.Context(0)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    p, q, vm = dev(batch.p_inj), dev(batch.q_inj), dev(batch.vm_set)
+    yv = dev(net.ybus_switch(on))
+    B = batch.batch
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        for kind in ("shared", "switch"):
+            if kind == "shared":
+                fn = lambda: net.solve(p, q, vm, precision=pf.precision(prec))  # noqa: E731
+            else:
+                fn = lambda: net.solve_yvals(p, q, vm, yv, precision=pf.precision(prec))  # noqa: E731
+            ms, _, out = time_steps(fn, steps, warmup)
+            conv = int(out.converged.sum().item())
+            mean_ms = float(ms.mean())
+            runs[f"{prec}_{kind}"] = {
+                "value": conv / (mean_ms * 1e-3), "ms_per_step": mean_ms, "converged": conv,
+                "newton_iters_mean": float(out.newton_iters.double().mean().item()),
+                "gmres_iters_mean": float(out.gmres_iters.double().mean().item()),
+                "algorithmic_bytes_per_launch": float(out.work_bytes.sum().item()),
+                "achieved_GBs": float(out.work_bytes.sum().item()) / (mean_ms * 1e-3) / 1e9}
+            print(f"[switch] {prec} {kind} {mean_ms:.3f} ms, {conv} converged, "
+                  f"gmres {runs[f'{prec}_{kind}']['gmres_iters_mean']:.1f}", file=sys.stderr, flush=True)
+    r = runs["fp64_switch"]
+    net.close()
+    ctx.close()
+    return {"metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"tx2000 N-1 actions: one branch out per scenario, batch {B}",
+                       "global_batch": B},
+            "runs": runs}
+
+
 def bench_feeder_sizes(steps: int, warmup: int) -> dict:
     """Dense Z product against the sparse Y_NN factor as the feeder grows (batch 1024, both precisions)."""
     import torch
@@ -494,7 +541,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tx2000",
-                    choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep", "feeder_sizes"])
+                    choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep", "feeder_sizes",
+                             "tx2000_switch"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--streams", default="1,2,1",
@@ -526,6 +574,8 @@ def main() -> int:
         line = bench_sweep(a.steps, a.warmup)
     elif a.workload == "feeder_sizes":
         line = bench_feeder_sizes(a.steps, a.warmup)
+    elif a.workload == "tx2000_switch":
+        line = bench_tx_switch(a.steps, a.warmup)
     else:
         line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
     print(json.dumps(line), flush=True)

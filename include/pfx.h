@@ -162,6 +162,44 @@ pf_status pf_tx_solve(pf_tx_network* net, const pf_opts* opts, int32_t batch, in
                       uint8_t* converged, double* final_mismatch, double* work_bytes,
                       pf_stream stream);
 
+/* Batched Newton-Raphson as pf_tx_solve, with each scenario's own Ybus values
+ * on the network's sparsity pattern: topology and parameter actions such as
+ * branch switching, one per scenario (the batches of candidate operating
+ * actions that Sec. I motivates).  y_vals: device, [batch][ldy] complex
+ * (re, im interleaved, 2 ldy doubles per scenario, ldy >= the nnz given at
+ * network creation), the values of the CSR entries given at creation, in
+ * that order (duplicates are summed as at creation; an entry may be zero).
+ * The mismatch (eq. (2)) and the Jacobian-vector products use the scenario's
+ * values; the preconditioner of eq. (7) stays the one factorised from the
+ * network's own values (an approximate left preconditioner only changes
+ * how fast GMRES converges, not the Newton step it converges to).  The values
+ * are first copied into the kernel's layout (FP64, plus an FP32 copy for
+ * PF_MIXED) in network-owned workspace, which grows to batch x the stored
+ * entries of Ybus.  work_bytes adds the scenario's Ybus entries per
+ * mismatch (16 bytes each) and per Jacobian-vector product (2w bytes each).
+ * A scenario whose actions leave the Jacobian singular (an islanded bus)
+ * reports converged = 0.
+ * Errors: as pf_tx_solve; PF_INVALID_ARG for ldy < nnz or null y_vals. */
+pf_status pf_tx_solve_yvals(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
+                            const double* p_inj, const double* q_inj, const double* vm_set, int64_t ldy,
+                            const double* y_vals, double* v_out, int32_t* newton_iters,
+                            int32_t* gmres_iters, uint8_t* converged, double* final_mismatch,
+                            double* work_bytes, pf_stream stream);
+
+/* Per-scenario Ybus values for branch switching, for pf_tx_solve_yvals: for
+ * each scenario s, y_vals[s] = the given Ybus (CSR as for
+ * pf_tx_network_create) minus the pi-model stamps (Sec. II-A) of the branches
+ * k with branch_on[s * n_branch + k] == 0.  The pattern is kept: the entries
+ * of a switched-out branch keep their places (zero off the diagonal when no
+ * other branch is parallel to it).  All pointers host; y_vals
+ * [batch][2 ldy] doubles, caller allocated, ldy >= nnz.
+ * Errors: PF_INVALID_ARG (bus index out of range, a branch whose four entries
+ * are not all in the pattern, zero impedance, ldy < nnz). */
+pf_status pf_tx_ybus_switch(int32_t n_bus, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* y_re, const double* y_im, int32_t n_branch, const int32_t* f,
+                            const int32_t* t, const double* r, const double* x, const double* b,
+                            int32_t batch, const uint8_t* branch_on, int64_t ldy, double* y_vals);
+
 /* Branch loss L_b = sum over branches of |I_f|^2 with the from-end current
  * I_f = (y_s + j b/2) V_f - y_s V_t, for voltages v (device complex
  * [batch][ld]).  Outputs (device): loss[batch] and, if dl_dv is not null, the

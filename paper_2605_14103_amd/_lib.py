@@ -61,6 +61,10 @@ _SIGS = [
     ("pf_tx_network_info", c_int32, [P, I32P, I32P, I32P, I32P, I32P, I32P, I32P]),
     ("pf_tx_solve", c_int32,
      [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, P, P, P, P, P, P, P]),
+    ("pf_tx_solve_yvals", c_int32,
+     [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, c_int64, P, P, P, P, P, P, P, P]),
+    ("pf_tx_ybus_switch", c_int32,
+     [c_int32, c_int32, P, P, P, P, c_int32, P, P, P, P, P, c_int32, P, c_int64, P]),
     ("pf_tx_branch_loss", c_int32, [P, c_int32, c_int64, P, P, P, P]),
     ("pf_tx_adjoint", c_int32, [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, P, P, P, P]),
     ("pf_dist_ybus_from_segments", c_int32,

@@ -102,45 +102,142 @@ pf_status pf_tx_network_info(const pf_tx_network* h, int32_t* n_bus, int32_t* n_
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, const double* p_inj,
+              const double* q_inj, const double* vm_set, int64_t ldy, const double* y_vals, double* v_out,
+              int32_t* newton_iters, int32_t* gmres_iters, uint8_t* converged, double* final_mismatch,
+              double* work_bytes, pf_stream stream) {
+  TxNetwork* net = tx_of(h);
+  const pf_opts o = resolve_opts(opts);
+  check_ld(batch, ld, net->n);
+  if (batch == 0) return;
+  require(p_inj && q_inj && vm_set && v_out && newton_iters && converged, "null required pointer");
+  activate(net->ctx);
+  const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  const bool mixed = o.precision == PF_MIXED;
+  const int64_t dstride = nr_ws_doubles(*net);
+  const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
+  net->ws_d.ensure(net->ctx, (size_t)batch * dstride * sizeof(double));
+  net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
+  NRLaunch a{};
+  if (y_vals) {
+    // FP64 layout copy, then (mixed) the FP32 copy behind it
+    const size_t n64 = (size_t)batch * net->y_entries;
+    net->ws_y.ensure(net->ctx, n64 * sizeof(double2) + (mixed ? n64 * sizeof(float2) : 0));
+    double2* y64 = net->ws_y.as<double2>();
+    float2* y32 = mixed ? reinterpret_cast<float2*>(y64 + n64) : nullptr;
+    launch_y_gather(*net, batch, ldy, y_vals, y64, y32, hs);
+    a.yv64 = y64;
+    a.yvT = mixed ? static_cast<const void*>(y32) : static_cast<const void*>(y64);
+    a.yv_stride = net->y_entries;
+    a.yv_nnz = net->nnz;
+  }
+  a.batch = batch;
+  a.ld = ld;
+  a.p_inj = p_inj;
+  a.q_inj = q_inj;
+  a.vm_set = vm_set;
+  a.v_out = v_out;
+  a.newton_iters = newton_iters;
+  a.gmres_iters = gmres_iters;
+  a.converged = converged;
+  a.final_mismatch = final_mismatch;
+  a.work_bytes = work_bytes;
+  a.tol = o.tol;
+  a.diverge = o.diverge;
+  a.rtol = o.gmres_rtol;
+  a.max_newton = o.max_newton;
+  a.restart = o.gmres_restart;
+  a.max_restarts = o.gmres_max_restarts;
+  a.ws_d = net->ws_d.as<double>();
+  a.ws_d_stride = dstride;
+  a.ws_basis = net->ws_basis.as<void>();
+  a.ws_b_stride = bstride;
+  launch_nr(*net, mixed, a, hs);
+}
+
+}  // namespace
+
+extern "C" {
+
 pf_status pf_tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld,
                       const double* p_inj, const double* q_inj, const double* vm_set, double* v_out,
                       int32_t* newton_iters, int32_t* gmres_iters, uint8_t* converged,
                       double* final_mismatch, double* work_bytes, pf_stream stream) {
   return guarded([&] {
-    TxNetwork* net = tx_of(h);
-    const pf_opts o = resolve_opts(opts);
-    check_ld(batch, ld, net->n);
-    if (batch == 0) return;
-    require(p_inj && q_inj && vm_set && v_out && newton_iters && converged, "null required pointer");
-    activate(net->ctx);
-    const bool mixed = o.precision == PF_MIXED;
-    const int64_t dstride = nr_ws_doubles(*net);
-    const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
-    net->ws_d.ensure(net->ctx, (size_t)batch * dstride * sizeof(double));
-    net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
-    NRLaunch a{};
-    a.batch = batch;
-    a.ld = ld;
-    a.p_inj = p_inj;
-    a.q_inj = q_inj;
-    a.vm_set = vm_set;
-    a.v_out = v_out;
-    a.newton_iters = newton_iters;
-    a.gmres_iters = gmres_iters;
-    a.converged = converged;
-    a.final_mismatch = final_mismatch;
-    a.work_bytes = work_bytes;
-    a.tol = o.tol;
-    a.diverge = o.diverge;
-    a.rtol = o.gmres_rtol;
-    a.max_newton = o.max_newton;
-    a.restart = o.gmres_restart;
-    a.max_restarts = o.gmres_max_restarts;
-    a.ws_d = net->ws_d.as<double>();
-    a.ws_d_stride = dstride;
-    a.ws_basis = net->ws_basis.as<void>();
-    a.ws_b_stride = bstride;
-    launch_nr(*net, mixed, a, reinterpret_cast<hipStream_t>(stream));
+    tx_solve(h, opts, batch, ld, p_inj, q_inj, vm_set, 0, nullptr, v_out, newton_iters, gmres_iters, converged,
+             final_mismatch, work_bytes, stream);
+  });
+}
+
+pf_status pf_tx_solve_yvals(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld,
+                            const double* p_inj, const double* q_inj, const double* vm_set, int64_t ldy,
+                            const double* y_vals, double* v_out, int32_t* newton_iters, int32_t* gmres_iters,
+                            uint8_t* converged, double* final_mismatch, double* work_bytes, pf_stream stream) {
+  return guarded([&] {
+    const TxNetwork* net = tx_of(h);
+    require(ldy >= net->caller_nnz, "ldy must be at least nnz (" + std::to_string(net->caller_nnz) + ")");
+    require(y_vals != nullptr || batch == 0, "y_vals must not be null");
+    tx_solve(h, opts, batch, ld, p_inj, q_inj, vm_set, ldy, y_vals, v_out, newton_iters, gmres_iters,
+             converged, final_mismatch, work_bytes, stream);
+  });
+}
+
+pf_status pf_tx_ybus_switch(int32_t n_bus, int32_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
+                            const double* y_re, const double* y_im, int32_t n_branch, const int32_t* f,
+                            const int32_t* t, const double* r, const double* x, const double* b, int32_t batch,
+                            const uint8_t* branch_on, int64_t ldy, double* y_vals) {
+  return guarded([&] {
+    require(n_bus >= 1 && nnz >= 0 && n_branch >= 0 && batch >= 0, "bad sizes");
+    require(ldy >= nnz, "ldy must be at least nnz");
+    require(row_ptr && (nnz == 0 || (col_idx && y_re && y_im)), "null CSR array");
+    if (n_branch > 0) require(f && t && r && x && b, "null branch array");
+    if (batch > 0) require(branch_on && y_vals, "null branch_on or y_vals");
+    require(row_ptr[0] == 0 && row_ptr[n_bus] == nnz, "row_ptr must run from 0 to nnz");
+    auto find = [&](int i, int j) {
+      require(i >= 0 && i < n_bus && j >= 0 && j < n_bus, "branch bus index out of range");
+      for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+        if (col_idx[p] == j) return p;
+      fail(PF_INVALID_ARG, "branch (" + std::to_string(i) + ", " + std::to_string(j) + ") has no entry in the pattern");
+      return -1;
+    };
+    // the four entries each branch stamps and what it adds there
+    struct Stamp {
+      int ff, tt, ft, tf;
+      std::complex<double> diag, off;
+    };
+    std::vector<Stamp> st(n_branch);
+    for (int k = 0; k < n_branch; ++k) {
+      require(f[k] != t[k], "a branch must join two different buses");
+      const std::complex<double> z(r[k], x[k]);
+      require(std::abs(z) > 0, "zero branch impedance");
+      const std::complex<double> ys = 1.0 / z;
+      st[k] = {find(f[k], f[k]), find(t[k], t[k]), find(f[k], t[k]), find(t[k], f[k]),
+               ys + std::complex<double>(0.0, 0.5 * b[k]), -ys};
+    }
+    for (int s = 0; s < batch; ++s) {
+      double* out = y_vals + 2 * ldy * (int64_t)s;
+      for (int p = 0; p < nnz; ++p) {
+        out[2 * p] = y_re[p];
+        out[2 * p + 1] = y_im[p];
+      }
+      const uint8_t* on = branch_on + (int64_t)n_branch * s;
+      for (int k = 0; k < n_branch; ++k) {
+        if (on[k]) continue;
+        const Stamp& q = st[k];
+        for (int p : {q.ff, q.tt}) {
+          out[2 * p] -= q.diag.real();
+          out[2 * p + 1] -= q.diag.imag();
+        }
+        for (int p : {q.ft, q.tf}) {
+          out[2 * p] -= q.off.real();
+          out[2 * p + 1] -= q.off.imag();
+        }
+      }
+    }
   });
 }
 

@@ -517,11 +517,14 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
 }
 
 // w <- J w, the Jacobian of the mismatch at the current V (with I = Ybus V).
-// Ends with a barrier.
+// yv: the scenario's own Ybus values (layout of net.yT), or null for the
+// network's.  Ends with a barrier.
 template <typename T, int BLOCK, int KB>
-__device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB], T* lds) {
+__device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB], T* lds,
+                    const typename Vec2<T>::type* yv) {
   using T2 = typename Vec2<T>::type;
-  const TxDev<T> net = load_desc(netp);
+  TxDev<T> net = load_desc(netp);
+  if (yv) net.yT.val = yv;
   constexpr int NW = BLOCK / WAVE;
   const unsigned nth = net.nth, npq = net.npq;
   T2* dv = reinterpret_cast<T2*>(lds);
@@ -628,11 +631,14 @@ __device__ T subtract_proj(const Basis<T, BLOCK, KB>& basis, int nv, T (&w)[2 * 
 }
 
 // Mismatch at the current (theta, |V|): writes V, 1/|V|, I and F to the
-// workspace and returns max |F| (NaN if any entry is NaN).  Ends with a barrier.
+// workspace and returns max |F| (NaN if any entry is NaN).  yv: the scenario's
+// own Ybus values (layout of net.y64), or null.  Ends with a barrier.
 template <typename T, int BLOCK, int KB>
-__device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double2* vs, double* part) {
+__device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double2* vs, double* part,
+                           const double2* yv) {
   constexpr int NW = BLOCK / WAVE;
-  const TxDev<T> net = load_desc(netp);
+  TxDev<T> net = load_desc(netp);
+  if (yv) net.y64.val = yv;
   const unsigned nth = net.nth, npq = net.npq;
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
@@ -688,10 +694,13 @@ struct ByteModel {
   // V and I (four reals per bus) read by a Jacobian-vector product: FP64, or
   // their FP32 copies for an FP32 inner solve
   double vi_n;
-  __device__ double jvp() const { return 2 * wm + vi_n; }
+  // per-scenario Ybus entries read by a Jacobian-vector product and by a
+  // mismatch evaluation (zero when the network's shared values are used)
+  double yj = 0.0, ym = 0.0;
+  __device__ double jvp() const { return 2 * wm + vi_n + yj; }
   __device__ double pre() const { return 2 * wm + n8; }
   __device__ double orth_pass(int j) const { return (2.0 * j + 3.0) * wm; }
-  __device__ double mismatch() const { return 4 * n8 + 2 * m8; }
+  __device__ double mismatch() const { return 4 * n8 + 2 * m8 + ym; }
   __device__ double update() const { return 2 * m8; }
 };
 
@@ -904,7 +913,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
   }
 
-  auto apply_j = [&](T (&w)[K]) { jvp<T, BLOCK, KB>(netp, ws, w, s.xs); };
+  using T2 = typename Vec2<T>::type;
+  const double2* yv64 = a.yv64 ? a.yv64 + (int64_t)b * a.yv_stride : nullptr;
+  const T2* yvT = a.yvT ? reinterpret_cast<const T2*>(a.yvT) + (int64_t)b * a.yv_stride : nullptr;
+  auto apply_j = [&](T (&w)[K]) { jvp<T, BLOCK, KB>(netp, ws, w, s.xs, yvT); };
   auto apply_m = [&](T (&w)[K]) { precond<T, BLOCK, KB>(netp, ws, w, s); };
 
   int newton = 0, gtotal = 0;
@@ -913,9 +925,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   double work = 0.0;
   int par = 0;
   for (;;) {
-    fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW);
+    fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW, yv64);
     const TxDev<T> net = load_desc(netp);
-    const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n, 4.0 * sizeof(T) * n};
+    const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n, 4.0 * sizeof(T) * n,
+                       2.0 * sizeof(T) * a.yv_nnz, 16.0 * a.yv_nnz};
     work += bm.mismatch();
     par ^= 1;
     if (!(fnorm <= a.diverge)) break;
@@ -1251,6 +1264,35 @@ void nr_shape(int n, int* block, int* kb) { dispatch_shape(n, ShapeOf{block, kb}
 int64_t nr_padded_rows(const TxNetwork& net) { return 2 * (int64_t)net.nbp; }
 int64_t nr_ws_doubles(const TxNetwork& net) { return 13 * (int64_t)net.nbp; }
 int64_t adj_ws_doubles(const TxNetwork& net) { return nr_ws_doubles(net); }
+
+// One thread per (scenario, layout entry), grid-stride over the batch.
+__global__ __launch_bounds__(256) void y_gather_kernel(const int* sptr, const int* sidx, int64_t E, int batch,
+                                                       const double* yv, int64_t ldy, double2* out64,
+                                                       float2* out32) {
+  const int64_t total = E * batch;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int64_t b = t / E, q = t - b * E;
+    const double* src = yv + 2 * ldy * b;
+    double re = 0.0, im = 0.0;
+    for (int k = sptr[q]; k < sptr[q + 1]; ++k) {
+      const int e = sidx[k];
+      re += src[2 * e];
+      im += src[2 * e + 1];
+    }
+    out64[t] = make_double2(re, im);
+    if (out32) out32[t] = make_float2((float)re, (float)im);
+  }
+}
+
+void launch_y_gather(const TxNetwork& net, int batch, int64_t ldy, const double* y_vals, double2* yv64,
+                     float2* yv32, hipStream_t s) {
+  if (batch == 0 || net.y_entries == 0) return;
+  const int64_t total = net.y_entries * batch;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(y_gather_kernel, dim3((unsigned)blocks), dim3(256), 0, s, net.ysrc_ptr.as<int>(),
+                     net.ysrc_idx.as<int>(), net.y_entries, batch, y_vals, ldy, yv64, yv32);
+  PFX_HIP(hipGetLastError());
+}
 
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s) {
   if (a.batch == 0) return;

@@ -88,8 +88,14 @@ struct TxNetwork {
   EfBuffers bp, bpp;
   DeviceBuffer br_f, br_t, br_ys_re, br_ys_im, br_b;
   DeviceBuffer inc_ptr, inc_br;   // branches incident to each internal bus
+  // Caller CSR entries that sum into each entry of the y64 layout (for
+  // per-scenario values): entries src_idx[src_ptr[q] .. src_ptr[q + 1]) of
+  // the caller's CSR make layout entry q (none for padding).
+  int caller_nnz = 0;
+  int64_t y_entries = 0;
+  DeviceBuffer ysrc_ptr, ysrc_idx;
   // solve workspaces (grow-only); calls on one network must not overlap
-  DeviceBuffer ws_d, ws_basis, ws_adj;
+  DeviceBuffer ws_d, ws_basis, ws_adj, ws_y;
   // the device views themselves, resident in device memory so kernels take one pointer
   DeviceBuffer desc64, desc32;
   template <typename T>
@@ -123,7 +129,21 @@ struct NRLaunch {
   int64_t ws_d_stride;
   void* ws_basis;
   int64_t ws_b_stride;
+  // Per-scenario Ybus values in the layout of TxDev::y64 (yv_stride entries
+  // per scenario): FP64 for the mismatch and, for an FP32 inner solve, an FP32
+  // copy for the Jacobian-vector products (yvT == yv64 in FP64).  Null: the
+  // network's own values for every scenario.
+  const double2* yv64;
+  const void* yvT;
+  int64_t yv_stride;
+  double yv_nnz;  // entries counted by the byte model (0 with shared values)
 };
+
+// Gather per-scenario Ybus values given in the caller's CSR entry order
+// (complex [batch][ldy]) into the y64 layout, in FP64 and (yv32 not null) FP32;
+// padding entries are written as zero.
+void launch_y_gather(const TxNetwork& net, int batch, int64_t ldy, const double* y_vals, double2* yv64,
+                     float2* yv32, hipStream_t s);
 
 // Doubles of per-scenario FP64 workspace the NR kernel needs, and the padded
 // state length (2 nbp: an angle plane and a magnitude plane) of its vectors.

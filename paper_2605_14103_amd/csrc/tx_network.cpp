@@ -328,7 +328,33 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
         gtr[j].push_back({i, -yre[p], 0.0});
       }
     }
-  upload_sell(ctx, build_sell(yr, 4), true, net->y);
+  const SellHost hy = build_sell(yr, 4);
+  {
+    // Layout entry of each caller CSR entry: row i's p-th (sorted) internal
+    // entry sits at off[i / 64] + 64 p + i % 64.
+    const int64_t E = (int64_t)hy.col.size();
+    std::vector<std::vector<int>> src(E);
+    for (int e = 0; e < n_bus; ++e) {
+      const int i = net->ext2int[e];
+      for (int p = row_ptr[e]; p < row_ptr[e + 1]; ++p) {
+        const int j = net->ext2int[col_idx[p]];
+        const int* at = std::lower_bound(col.data() + ptr[i], col.data() + ptr[i + 1], j);
+        const int64_t q = hy.off[i / 64] + (int64_t)(at - (col.data() + ptr[i])) * 64 + i % 64;
+        src[q].push_back(p);
+      }
+    }
+    std::vector<int> sp(E + 1, 0), si;
+    for (int64_t q = 0; q < E; ++q) {
+      si.insert(si.end(), src[q].begin(), src[q].end());
+      sp[q + 1] = (int)si.size();
+    }
+    if (si.empty()) si.push_back(0);
+    net->caller_nnz = nnz;
+    net->y_entries = E;
+    net->ysrc_ptr = upload(ctx, sp);
+    net->ysrc_idx = upload(ctx, si);
+  }
+  upload_sell(ctx, hy, true, net->y);
   upload_sell(ctx, build_sell(ytr, 4), true, net->yt);
   upload_sell(ctx, build_sell(gr, 4), false, net->g);
   upload_sell(ctx, build_sell(gtr, 4), false, net->gt);

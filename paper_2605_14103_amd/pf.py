@@ -120,6 +120,9 @@ class TxNetwork:
                _hptr(yim), _hptr(bt), nbr, _hptr(f), _hptr(t), _hptr(r), _hptr(x), _hptr(b), byref(so), byref(h))
         self.h = h
         self.info = self._info()
+        k = nnz.value
+        self.csr = (ptr, col[:k].copy(), yre[:k].copy(), yim[:k].copy())
+        self.branches = (f, t, r, x, b)
 
     @classmethod
     def from_grid(cls, ctx: Context, grid, **setup) -> "TxNetwork":
@@ -158,6 +161,50 @@ class TxNetwork:
         L.call("pf_tx_solve", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
                _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters), _dptr(out.converged),
                _dptr(out.mismatch), _dptr(out.work_bytes), _stream(stream))
+        return out
+
+    def ybus_switch(self, branch_on: np.ndarray) -> np.ndarray:
+        """Per-scenario Ybus values (complex [batch][nnz], this network's CSR
+        order) with the branches where ``branch_on`` is 0 switched out; see
+        pf_tx_ybus_switch."""
+        on = np.ascontiguousarray(branch_on, dtype=np.uint8)
+        f, t, r, x, b = self.branches
+        if on.ndim != 2 or on.shape[1] != f.shape[0]:
+            raise ValueError(f"branch_on must be (batch, {f.shape[0]})")
+        ptr, col, yre, yim = self.csr
+        nnz = int(col.shape[0])
+        out = np.zeros((on.shape[0], nnz), dtype=np.complex128)
+        L.call("pf_tx_ybus_switch", self.n_bus, nnz, _hptr(ptr), _hptr(col), _hptr(yre), _hptr(yim),
+               int(f.shape[0]), _hptr(f), _hptr(t), _hptr(r), _hptr(x), _hptr(b), int(on.shape[0]), _hptr(on),
+               nnz, _hptr(out))
+        return out
+
+    def solve_yvals(self, p_inj: torch.Tensor, q_inj: torch.Tensor, vm_set: torch.Tensor, y_vals: torch.Tensor,
+                    *, stream=None, out: TxResult | None = None, **opts) -> TxResult:
+        """Batched Newton-Raphson with each scenario's own Ybus values (device complex
+        [batch][nnz] in this network's CSR order); see pf_tx_solve_yvals."""
+        n = self.n_bus
+        ld = _ld((p_inj, n, torch.float64, "p_inj"), (q_inj, n, torch.float64, "q_inj"),
+                 (vm_set, n, torch.float64, "vm_set"))
+        nnz = int(self.csr[1].shape[0])
+        B = int(p_inj.shape[0])
+        ldy = _ld((y_vals, nnz, torch.complex128, "y_vals"))
+        if int(y_vals.shape[0]) != B:
+            raise ValueError("y_vals must have one row per scenario")
+        dev = p_inj.device
+        if out is None:
+            out = TxResult(v=torch.empty((B, n), dtype=torch.complex128, device=dev),
+                           newton_iters=torch.empty(B, dtype=torch.int32, device=dev),
+                           gmres_iters=torch.empty(B, dtype=torch.int32, device=dev),
+                           converged=torch.empty(B, dtype=torch.uint8, device=dev),
+                           mismatch=torch.empty(B, dtype=torch.float64, device=dev),
+                           work_bytes=torch.empty(B, dtype=torch.float64, device=dev))
+        if B > 1 and out.v.stride(0) != ld:
+            raise ValueError("output rows must use the input row stride")
+        o = L.opts(**opts)
+        L.call("pf_tx_solve_yvals", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
+               ldy, _dptr(y_vals), _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters),
+               _dptr(out.converged), _dptr(out.mismatch), _dptr(out.work_bytes), _stream(stream))
         return out
 
     def branch_loss(self, v: torch.Tensor, *, grad: bool = True, stream=None):

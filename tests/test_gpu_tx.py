@@ -278,3 +278,105 @@ def test_every_workgroup_shape(ctx, n_bus, n_check):
         assert res.converged.cpu().numpy().all()
         _check_against_oracle(grid, batch, res, np.arange(n_check), precision)
     net.close()
+
+
+def _solve_yvals(net, batch, yv, **opts):
+    import torch
+    res = net.solve_yvals(to_dev(batch.p_inj), to_dev(batch.q_inj), to_dev(batch.vm_set), yv, **opts)
+    torch.cuda.synchronize()
+    return res
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_yvals_with_the_networks_own_values_is_bitwise_the_shared_solve(ctx, precision):
+    """Per-scenario values equal to the network's own (tiled, in rows padded past
+    nnz) give the shared-value solve bit for bit: same layout, same arithmetic."""
+    import torch
+    from paper_2605_14103_amd import pf
+    for cfg, B in ((tx.TX30, 64), (tx.TX2000, 48)):
+        grid = tx.make_grid(cfg)
+        batch = tx.make_batch(grid, cfg, batch=B)
+        net = pf.TxNetwork.from_grid(ctx, grid)
+        base = net.csr[2] + 1j * net.csr[3]
+        nnz = base.shape[0]
+        yv = torch.zeros((B, nnz + 5), dtype=torch.complex128)
+        yv[:, :nnz] = torch.from_numpy(base)[None, :]
+        yv = yv.cuda()[:, :nnz]
+        say(f"{cfg.name} yvals identity {precision}: nnz {nnz}, ldy {yv.stride(0)}")
+        ref = _solve(net, batch, precision=pf.precision(precision))
+        res = _solve_yvals(net, batch, yv, precision=pf.precision(precision))
+        assert torch.equal(res.v, ref.v)
+        assert torch.equal(res.newton_iters, ref.newton_iters)
+        assert torch.equal(res.gmres_iters, ref.gmres_iters)
+        assert torch.equal(res.converged, ref.converged)
+        assert torch.equal(res.mismatch, ref.mismatch)
+        # the byte model adds the scenario's Ybus entries
+        assert (res.work_bytes > ref.work_bytes).all()
+        net.close()
+
+
+def _check_outages(grid, batch, on, res, cols, label):
+    v = res.v.cpu().numpy()
+    conv = res.converged.cpu().numpy()
+    mis = res.mismatch.cpu().numpy()
+    errs = []
+    for c in cols:
+        m = on[c].astype(bool)
+        Y = onr.ybus(grid.n_bus, grid.f[m], grid.t[m], grid.r[m], grid.x[m], grid.b[m])
+        ref = onr.nr_solve(Y, grid.bus_type, batch.p_inj[c], batch.q_inj[c], batch.vm_set[c])
+        assert ref.converged, f"oracle did not converge for scenario {c}"
+        assert conv[c] and mis[c] <= 1e-8
+        errs.append(angle_err(v[c:c + 1], ref.V[None, :]))
+    da = max(e[0] for e in errs)
+    dm = max(e[1] for e in errs)
+    say(f"{label}: {len(cols)} scenarios, max angle err {da:.2e} rad, max |V| err {dm:.2e} pu, "
+        f"newton {res.newton_iters.cpu().numpy()[cols].tolist()[:8]}, "
+        f"gmres {res.gmres_iters.cpu().numpy()[cols].tolist()[:8]}")
+    assert da <= TOL_A and dm <= TOL_V
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_branch_outages_against_oracle(ctx, precision):
+    """Topology-action batches: every scenario of the 30-bus grid with two
+    branches out, and sampled scenarios of the 2000-bus grid with one branch out
+    at batch 1024, each against the oracle solving with that scenario's own
+    admittance matrix."""
+    import torch
+    from paper_2605_14103_amd import pf
+    for cfg, n_out, cols in ((tx.TX30, 2, None), (tx.TX2000, 1, np.array([0, 1, 700, 1023]))):
+        grid = tx.make_grid(cfg)
+        batch = tx.make_batch(grid, cfg)
+        on = tx.make_outages(grid, batch.batch, n_out=n_out, seed=cfg.seed + 7)
+        net = pf.TxNetwork.from_grid(ctx, grid)
+        yv = torch.from_numpy(net.ybus_switch(on)).cuda()
+        res = _solve_yvals(net, batch, yv, precision=pf.precision(precision))
+        conv = res.converged.cpu().numpy()
+        say(f"{cfg.name} outages {precision}: converged {int(conv.sum())} of {batch.batch}")
+        _check_outages(grid, batch, on, res, np.arange(batch.batch) if cols is None else cols,
+                       f"{cfg.name} {n_out} out {precision}")
+        net.close()
+
+
+def test_yvals_argument_errors(ctx):
+    import torch
+    from paper_2605_14103_amd import _lib, pf
+    grid = tx.make_grid(tx.TX30)
+    batch = tx.make_batch(grid, tx.TX30, batch=4)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    nnz = net.csr[1].shape[0]
+    with pytest.raises(ValueError):  # rows shorter than nnz
+        _solve_yvals(net, batch, torch.zeros((4, nnz - 1), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(ValueError):  # one row per scenario
+        _solve_yvals(net, batch, torch.zeros((3, nnz), dtype=torch.complex128, device="cuda"))
+    # the C entry point itself rejects ldy < nnz and a null y_vals
+    o = _lib.opts()
+    import ctypes
+    st = _lib.lib().pf_tx_solve_yvals(net.h, ctypes.byref(o), 0, grid.n_bus, None, None, None, nnz - 1, None,
+                                      None, None, None, None, None, None, None)
+    assert st == _lib.PF_INVALID_ARG
+    p = to_dev(batch.p_inj)
+    st = _lib.lib().pf_tx_solve_yvals(net.h, ctypes.byref(o), 4, grid.n_bus, ctypes.c_void_p(p.data_ptr()),
+                                      ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(p.data_ptr()), nnz, None,
+                                      None, None, None, None, None, None, None)
+    assert st == _lib.PF_INVALID_ARG
+    net.close()

@@ -127,11 +127,13 @@ def test_large_feeder_many_slots(ctx):
 def test_sparse_variant(ctx, precision):
     """The sparse variant (Y_NN^-1 r by the L D L^T of Y_NN instead of the dense
     Z product) against the oracle: a small feeder in full, the 300-bus feeder
-    at its full batch (sampled) and the 700-bus feeder."""
+    at its full batch (sampled), and 700- and 908-bus feeders (2724 phase
+    nodes)."""
     from paper_2605_14103_amd import pf
     cases = [(fdm.FeederConfig("feeder40s", n_bus=40, max_depth=25, batch=33, seed=43), None),
              (fdm.FEEDER300, np.array([0, 1, 2047, 4095])),
-             (fdm.FeederConfig("feeder700s", n_bus=700, max_depth=30, batch=5, seed=701), None)]
+             (fdm.FeederConfig("feeder700s", n_bus=700, max_depth=30, batch=5, seed=701), None),
+             (fdm.FeederConfig("feeder908s", n_bus=908, max_depth=25, batch=3, seed=908), None)]
     for cfg, cols in cases:
         fd = fdm.make_feeder(cfg)
         batch = fdm.make_batch(fd, cfg)

@@ -124,3 +124,99 @@ def test_feeder_ybus_builder_matches_oracle_definition():
         E[a:a + 3, c:c + 3] -= y
         E[c:c + 3, a:a + 3] -= y
     assert np.max(np.abs(Y - E)) <= 1e-12 * np.max(np.abs(E))
+
+
+def _lib_ybus(grid):
+    """The library's CSR of a grid's admittance matrix (host arrays)."""
+    import ctypes
+
+    import numpy as np
+
+    P = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    n, nb = grid.n_bus, int(grid.f.shape[0])
+    cap = n + 2 * nb
+    ptr = np.zeros(n + 1, dtype=np.int32)
+    col = np.zeros(cap, dtype=np.int32)
+    yre = np.zeros(cap)
+    yim = np.zeros(cap)
+    nnz = ctypes.c_int32()
+    f, t = grid.f.astype(np.int32), grid.t.astype(np.int32)
+    _lib.call("pf_tx_ybus_from_branches", n, nb, P(f), P(t), P(grid.r), P(grid.x), P(grid.b), cap, P(ptr),
+              P(col), P(yre), P(yim), ctypes.byref(nnz))
+    k = nnz.value
+    return ptr, col[:k].copy(), yre[:k].copy(), yim[:k].copy()
+
+
+def _switch(grid, csr, on, ldy=None):
+    import ctypes
+
+    import numpy as np
+
+    P = lambda a: ctypes.c_void_p(a.ctypes.data)  # noqa: E731
+    ptr, col, yre, yim = csr
+    nnz = int(col.shape[0])
+    ldy = nnz if ldy is None else ldy
+    out = np.full((on.shape[0], ldy), np.nan, dtype=np.complex128)
+    f, t = grid.f.astype(np.int32), grid.t.astype(np.int32)
+    on = np.ascontiguousarray(on, dtype=np.uint8)
+    st = _lib.lib().pf_tx_ybus_switch(grid.n_bus, nnz, P(ptr), P(col), P(yre), P(yim), int(f.shape[0]), P(f),
+                                      P(t), P(grid.r), P(grid.x), P(grid.b), int(on.shape[0]), P(on), ldy,
+                                      P(out))
+    return st, out
+
+
+def test_ybus_switch_matches_oracle_admittance():
+    """Branch switching on the 30-bus grid: each scenario's values, read back as
+    a dense matrix, equal the oracle's admittance matrix built from the branches
+    left in service (two outages per scenario, plus the all-in-service case)."""
+    import numpy as np
+
+    from oracle import nr as onr
+    from workloads import transmission as tx
+
+    grid = tx.make_grid(tx.TX30)
+    csr = _lib_ybus(grid)
+    ptr, col = csr[0], csr[1]
+    on = tx.make_outages(grid, 12, n_out=2, seed=5)
+    on[0] = 1
+    st, vals = _switch(grid, csr, on, ldy=int(col.shape[0]) + 3)
+    assert st == _lib.PF_OK
+    assert np.isnan(vals[:, -3:]).all()  # padding of each row untouched
+    for s in range(on.shape[0]):
+        Y = np.zeros((grid.n_bus, grid.n_bus), dtype=complex)
+        for i in range(grid.n_bus):
+            for p in range(ptr[i], ptr[i + 1]):
+                Y[i, col[p]] += vals[s, p]
+        m = on[s].astype(bool)
+        ref = onr.ybus(grid.n_bus, grid.f[m], grid.t[m], grid.r[m], grid.x[m], grid.b[m]).toarray()
+        np.testing.assert_allclose(Y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    # all in service: the base values exactly
+    np.testing.assert_array_equal(vals[0, :col.shape[0]], csr[2] + 1j * csr[3])
+
+
+def test_ybus_switch_errors():
+    import ctypes
+
+    import numpy as np
+
+    from workloads import transmission as tx
+
+    grid = tx.make_grid(tx.TX30)
+    csr = _lib_ybus(grid)
+    on = np.ones((2, grid.f.shape[0]), dtype=np.uint8)
+    st, _ = _switch(grid, csr, on, ldy=int(csr[1].shape[0]) - 1)
+    assert st == _lib.PF_INVALID_ARG and b"ldy" in _lib.lib().pf_last_error()
+    # a branch whose entries are not in the pattern
+    import dataclasses
+    f = grid.f.copy()
+    t = grid.t.copy()
+    pairs = set(zip(f.tolist(), t.tolist())) | set(zip(t.tolist(), f.tolist()))
+    a, c = next((i, j) for i in range(grid.n_bus) for j in range(grid.n_bus) if i != j and (i, j) not in pairs)
+    f[0], t[0] = a, c
+    g2 = dataclasses.replace(grid, f=f, t=t)
+    st, _ = _switch(g2, csr, on)
+    assert st == _lib.PF_INVALID_ARG and b"pattern" in _lib.lib().pf_last_error()
+    # zero scenarios is a no-op
+    st, out = _switch(grid, csr, on[:0])
+    assert st == _lib.PF_OK and out.shape[0] == 0
+    del ctypes

@@ -102,3 +102,22 @@ def test_serving_trace():
     rate = (len(tr) - 1) / t[-1]
     assert abs(rate - 2000) / 2000 < 0.05
     assert set(r.network for r in tr) == {0, 1, 2}
+
+
+def test_outage_batches_keep_the_grid_connected():
+    import numpy as np
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    from workloads import transmission as tx
+
+    grid = tx.make_grid(tx.TX30)
+    for n_out in (0, 1, 3):
+        on = tx.make_outages(grid, 20, n_out=n_out, seed=11)
+        assert on.dtype == np.uint8 and on.shape == (20, grid.f.shape[0])
+        assert ((on == 0).sum(axis=1) == n_out).all()
+        for s in range(20):
+            m = on[s].astype(bool)
+            g = coo_matrix((np.ones(int(m.sum())), (grid.f[m], grid.t[m])), shape=(grid.n_bus, grid.n_bus))
+            assert connected_components(g, directed=False)[0] == 1
+    np.testing.assert_array_equal(tx.make_outages(grid, 5, 2, seed=1), tx.make_outages(grid, 5, 2, seed=1))

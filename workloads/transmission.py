@@ -258,3 +258,41 @@ def zero_load(grid: TxGrid, batch: int = 1) -> TxBatch:
     n = grid.n_bus
     return TxBatch(p_inj=np.zeros((batch, n)), q_inj=np.zeros((batch, n)),
                    vm_set=np.ones((batch, n)))
+
+
+def make_outages(grid: TxGrid, batch: int, n_out: int = 1, seed: int = 0) -> np.ndarray:
+    """Branch status per scenario for topology-action batches: ``branch_on``
+    uint8 [batch, n_branch], 1 = in service.  Each scenario takes ``n_out``
+    distinct branches out of service, drawn uniformly among those whose removal
+    keeps every bus connected to the slack (redrawn otherwise), so each
+    scenario stays a well-posed power flow.  Pure data generation (a graph
+    connectivity test, no electrical quantity)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    rng = np.random.default_rng(seed)
+    n, nb = grid.n_bus, int(grid.f.shape[0])
+    on = np.ones((batch, nb), dtype=np.uint8)
+
+    def connected(mask):
+        g = coo_matrix((np.ones(int(mask.sum())), (grid.f[mask], grid.t[mask])), shape=(n, n))
+        return connected_components(g, directed=False)[0] == 1
+
+    for s in range(batch):
+        mask = np.ones(nb, dtype=bool)
+        taken = 0
+        for _ in range(100 * max(n_out, 1)):
+            if taken == n_out:
+                break
+            k = int(rng.integers(0, nb))
+            if not mask[k]:
+                continue
+            mask[k] = False
+            if connected(mask):
+                taken += 1
+            else:
+                mask[k] = True
+        if taken != n_out:
+            raise ValueError(f"could not take {n_out} branches out without islanding a bus")
+        on[s] = mask
+    return on
