@@ -177,6 +177,15 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
             "algorithmic_bytes_per_launch": work,
             "achieved_GBs": work / (mean_ms * 1e-3) / 1e9,
         }
+    if grid.n_bus <= 800:
+        # the direct Newton step (per-scenario sparse LU, FP64) on the same batch
+        out = net.solve(p, q, vm, nr_direct=1)
+        ms, wall, out = time_steps(lambda: net.solve(p, q, vm, out=out, nr_direct=1), steps, warmup)
+        conv = int(out.converged.sum().item())
+        runs["fp64_direct"] = {
+            "value": conv / (float(ms.mean()) * 1e-3), "ms_per_step": float(ms.mean()), "converged": conv,
+            "latency_ms": {"p50": float(np.percentile(ms, 50)), "p99": float(np.percentile(ms, 99))},
+            "newton_iters_mean": float(out.newton_iters.double().mean().item())}
     # spot parity against the oracle (the rate counts only converged solves)
     from oracle import nr as onr
     cols = np.array([0, B - 1])
@@ -205,6 +214,7 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
                      "bytes_per_launch": r["algorithmic_bytes_per_launch"]},
         "fp64": runs["fp64"], "mixed": runs["mixed"],
         "mixed_vs_fp64": runs["mixed"]["value"] / r["value"],
+        "direct": runs.get("fp64_direct"),
         "network": net.info,
     }
     if cpu is not None:

@@ -77,6 +77,11 @@ typedef struct pf_opts {
   int32_t zbus_sparse;        /* 0: dense product Z r on the matrix cores (default); 1: Y_NN^-1 r
                                  by level-scheduled solves with a sparse L D L^T of Y_NN (the
                                  sparse variant named as future work in Sec. II-B) */
+  /* transmission Newton step */
+  int32_t nr_direct;          /* 0: preconditioned GMRES (default); 1: exact Newton step by a
+                                 per-scenario sparse LU of J on a shared symbolic analysis (the
+                                 sparse direct outlook of Sec. IV), always in FP64, for networks
+                                 whose factor fits the per-scenario limit (12288 values) */
 } pf_opts;
 
 void pf_opts_default(pf_opts* out);

@@ -75,6 +75,7 @@ pf_opts resolve_opts(const pf_opts* o) {
   require(r.factor_max_levels >= 1, "factor_max_levels must be >= 1");
   require(r.factor_max_core >= 0 && r.factor_max_core <= 2048, "factor_max_core must be 0..2048");
   require(r.zbus_sparse == 0 || r.zbus_sparse == 1, "zbus_sparse must be 0 or 1");
+  require(r.nr_direct == 0 || r.nr_direct == 1, "nr_direct must be 0 or 1");
   return r;
 }
 
@@ -121,6 +122,7 @@ void pf_opts_default(pf_opts* o) {
   o->factor_max_levels = 8;
   o->factor_max_core = 384;
   o->zbus_sparse = 0;
+  o->nr_direct = 0;
 }
 
 const char* pf_last_error(void) { return g_last_error.c_str(); }

@@ -73,7 +73,9 @@ pf_status pf_engine_create(pf_context* c, pf_tx_network* tx, pf_dist_network* di
     const Context* owner = kind == 0 ? static_cast<TxNetwork*>(net)->ctx : static_cast<DistNetwork*>(net)->ctx;
     require(owner == ctx, "the network belongs to another context");
     activate(ctx);
-    Engine* e = engine_create(ctx, kind, net, hbm_bytes, n_streams, resolve_opts(opts));
+    const pf_opts o = resolve_opts(opts);
+    require(o.nr_direct == 0, "the serving engine runs the GMRES Newton step (nr_direct must be 0)");
+    Engine* e = engine_create(ctx, kind, net, hbm_bytes, n_streams, o);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
       ctx->engines.insert(e);

@@ -117,11 +117,13 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   require(p_inj && q_inj && vm_set && v_out && newton_iters && converged, "null required pointer");
   activate(net->ctx);
   const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
-  const bool mixed = o.precision == PF_MIXED;
+  const bool direct = o.nr_direct == 1;
+  if (direct) ensure_direct(*net);
+  const bool mixed = o.precision == PF_MIXED && !direct;
   const int64_t dstride = nr_ws_doubles(*net);
   const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
   net->ws_d.ensure(net->ctx, (size_t)batch * dstride * sizeof(double));
-  net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
+  if (!direct) net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
   NRLaunch a{};
   if (y_vals) {
     // FP64 layout copy, then (mixed) the FP32 copy behind it
@@ -156,7 +158,8 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   a.ws_d_stride = dstride;
   a.ws_basis = net->ws_basis.as<void>();
   a.ws_b_stride = bstride;
-  launch_nr(*net, mixed, a, hs);
+  if (direct) launch_nr_direct(*net, a, hs);
+  else launch_nr(*net, mixed, a, hs);
 }
 
 }  // namespace

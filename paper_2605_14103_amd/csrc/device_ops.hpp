@@ -175,6 +175,17 @@ __device__ __forceinline__ void settle(T& x) {
   asm volatile("" : "+v"(x));
 }
 
+__device__ __forceinline__ int2 cld(const int2* base, unsigned i) {
+  typedef int __attribute__((ext_vector_type(2))) I2;
+  typedef __attribute__((address_space(4))) const char CC;
+  typedef __attribute__((address_space(4))) const I2 CT;
+  const I2 v = *(CT*)((CC*)base + i * 8u);
+  int2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
+
 __device__ __forceinline__ int4 cld(const int4* base, unsigned i) {
   typedef int __attribute__((ext_vector_type(4))) I4;
   typedef __attribute__((address_space(4))) const char CC;

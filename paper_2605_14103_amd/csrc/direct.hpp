@@ -1,0 +1,41 @@
+// Shared symbolic analysis for the direct Newton step: the pattern of the
+// polar Jacobian of eq. (4) (states theta over Theta, |V| over Q), a
+// minimum-degree order of it, its fill under LU without pivoting and the
+// static schedule of the numeric factorisation, which then runs per scenario
+// (the batched sparse direct solve the paper points to as an outlook, Sec. IV).
+//
+// J is structurally symmetric (J[a][b] is nonzero where the buses of states a
+// and b are equal or joined by a branch), so L and U share one pattern: for
+// pivot k, S(k) lists the later positions i with L[i][k] != 0, which are also
+// the later positions j with U[k][j] != 0.  Values of one scenario's factor
+// are stored as [diagonal U[k][k] (m) | L columns by pivot, unscaled
+// (L[i][k] U[k][k]) | U rows by pivot].
+#pragma once
+
+#include <vector>
+
+namespace pfx {
+
+struct TxNetwork;
+
+struct DirectLuHost {
+  int m = 0, n_s = 0, n_val = 0;
+  std::vector<int> fpos;     // [2 nbp]: factor position of theta_i (i) and |V|_i (nbp + i), -1 if none
+  std::vector<int> soff;     // [m + 1]: S(k) = sidx[soff[k] .. soff[k + 1])
+  std::vector<int> sidx;
+  std::vector<int> uoff;     // [m + 1]: updates of pivot k, pairs (a, b) of S(k) x S(k), a-major
+  std::vector<int> upd;      // value index of entry (S_a, S_b)
+  std::vector<int> ucp;      // [m + 1]: column k of U above the diagonal
+  std::vector<int> ucol;     // pairs (row, value index)
+  std::vector<int> je;       // J entries, 4 ints each: (value index | kind << 28, bus i, bus k, Ybus layout index)
+};
+
+// Values of the factor held per scenario beyond which the direct step is
+// refused (they live in LDS during the factorisation).
+constexpr int DIRECT_MAX_VALUES = 12288;
+
+// Builds the analysis for a registered network.  Throws PfError
+// (PF_INVALID_ARG) when the factor would exceed DIRECT_MAX_VALUES values.
+DirectLuHost build_direct_lu(const TxNetwork& net);
+
+}  // namespace pfx

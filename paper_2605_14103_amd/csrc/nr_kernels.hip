@@ -980,6 +980,225 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 }
 
 // ---------------------------------------------------------------------------
+// Direct Newton step (FP64): per scenario, the Jacobian of eq. (4) is formed
+// in the shared fill pattern (direct.hpp), factorised by LU without pivoting
+// in the shared minimum-degree order and solved by the two triangular
+// solves; one workgroup per scenario with the factor in LDS.  The pivots run
+// in order; within a pivot, its rank-one update of the trailing entries
+// (distinct targets) is spread over the workgroup, as are the entries of each
+// backward-solve step; the forward solve runs inside the factorisation.
+//
+// Entries of J for a Ybus entry (i, k), with a = V_i conj(Y_ik V_k) and
+// c = V_i conj(I_i) (the bus power):  i != k: dS_i/dtheta_k = -j a,
+// dS_i/d|V_k| = a / |V_k|;  i == k: dS_i/dtheta_i = j (c - a),
+// dS_i/d|V_i| = (a + c) / |V_i|.  Theta rows take the real part, Q rows the
+// imaginary part (kind = 2 row type + column type).
+template <int BLOCK, int KB>
+__global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* __restrict__ netp, DirectDev d,
+                                                          NRLaunch a) {
+  constexpr int NW = BLOCK / WAVE;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  int n, npq, nth;
+  {
+    const TxDev<double> net = load_desc(netp);
+    n = net.n;
+    npq = net.npq;
+    nth = net.nth;
+  }
+  constexpr int NBP = KB * BLOCK;
+  const int m = d.m, ns = d.n_s;
+  double2* vs = reinterpret_cast<double2*>(smem);
+  double2* is = vs + NBP;
+  double* red = reinterpret_cast<double*>(is + NBP);
+  double* val = red + 2 * NW;
+  double* rhs = val + d.n_val;
+  double* xs = rhs + m;
+
+  const Ws<BLOCK, KB> ws{make_buf(a.ws_d + (int64_t)b * a.ws_d_stride)};
+  const Buf P = make_buf(a.p_inj + (int64_t)b * a.ld);
+  const Buf Q = make_buf(a.q_inj + (int64_t)b * a.ld);
+  const Buf VS = make_buf(a.vm_set + (int64_t)b * a.ld);
+  {
+    const TxDev<double> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      double p = 0.0, q = 0.0, vsp = 1.0;
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 8u;
+        p = bld<double>(P, e, 0);
+        q = bld<double>(Q, e, 0);
+        if ((int)i >= npq) vsp = bld<double>(VS, e, 0);
+      }
+      ws.st(TH, k, 0.0);
+      ws.st(VM, k, vsp);
+      ws.st(PIN, k, p);
+      ws.st(QIN, k, q);
+    }
+  }
+  const double2* yv = a.yv64 ? a.yv64 + (int64_t)b * a.yv_stride : nullptr;
+
+  int newton = 0;
+  bool conv = false;
+  double fnorm = 0.0, work = 0.0;
+  int par = 0;
+  for (;;) {
+    fnorm = mismatch<double, BLOCK, KB>(netp, ws, vs, red + par * NW, yv);
+    work += 32.0 * n + 16.0 * m + 16.0 * a.yv_nnz;
+    par ^= 1;
+    if (!(fnorm <= a.diverge)) break;
+    if (fnorm <= a.tol) {
+      conv = true;
+      break;
+    }
+    if (newton >= a.max_newton) break;
+    // own buses' I and -F into LDS (F in factor order); factor values cleared
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      is[i] = make_double2(ws.ld(IRE, k), ws.ld(IIM, k));
+      if ((int)i < nth) rhs[cld(d.fpos, i)] = -ws.ld(FP, k);
+      if ((int)i < npq) rhs[cld(d.fpos, (unsigned)NBP + i)] = -ws.ld(FP, KB + k);
+    }
+    for (int q = tid; q < d.n_val; q += BLOCK) val[q] = 0.0;
+    __syncthreads();
+    {
+      const TxDev<double> net = load_desc(netp);
+      const double2* yvals = yv ? yv : net.y64.val;
+      for (int e = tid; e < d.n_je; e += BLOCK) {
+        const int4 E = cld(d.je, (unsigned)e);
+        const int pos = E.x & 0x0fffffff, kind = (int)((unsigned)E.x >> 28);
+        const double2 vi = vs[E.y], vk = vs[E.z], y = cld(yvals, (unsigned)E.w);
+        const double tr = y.x * vk.x - y.y * vk.y, ti = y.x * vk.y + y.y * vk.x;  // Y_ik V_k
+        double ar = vi.x * tr + vi.y * ti, ai = vi.y * tr - vi.x * ti;            // V_i conj(Y_ik V_k)
+        double dtr, dti, dvr, dvi;
+        if (E.y != E.z) {
+          const double ivk = 1.0 / sqrt(vk.x * vk.x + vk.y * vk.y);
+          dtr = ai;
+          dti = -ar;
+          dvr = ar * ivk;
+          dvi = ai * ivk;
+        } else {
+          const double2 ii = is[E.y];
+          const double cr = vi.x * ii.x + vi.y * ii.y, ci = vi.y * ii.x - vi.x * ii.y;
+          const double ivi = 1.0 / sqrt(vi.x * vi.x + vi.y * vi.y);
+          dtr = -(ci - ai);
+          dti = cr - ar;
+          dvr = (ar + cr) * ivi;
+          dvi = (ai + ci) * ivi;
+        }
+        val[pos] = kind == 0 ? dtr : kind == 1 ? dvr : kind == 2 ? dti : dvi;
+      }
+    }
+    __syncthreads();
+    // LU in factor order with the forward solve L y = -F fused in: L[S(k), k]
+    // stays unscaled (its entries hold L U[k][k]) and is divided by the pivot
+    // where used, so each pivot is one phase: the rank-one update of its
+    // trailing entries (distinct targets) and the update of rhs[S(k)] read
+    // only pivot k's own row, column and rhs[k], all final after the barrier
+    // that closed the previous pivot.  A thread's first update target and row
+    // index of the next pivot are loaded while the current pivot computes.
+    if (m > 0) {  // (m = 0 converges at the first mismatch; kept for clarity)
+      int s0 = cld(d.soff, 0u), s1 = cld(d.soff, 1u), u0 = cld(d.uoff, 0u);
+      int cnt = s1 - s0;
+      int pt = tid < cnt * cnt ? cld(d.upd, (unsigned)(u0 + tid)) : 0;
+      int pr = tid < cnt ? cld(d.sidx, (unsigned)(s0 + tid)) : 0;
+      for (int k = 0; k < m; ++k) {
+        const bool more = k + 1 < m;
+        const int s2 = more ? cld(d.soff, (unsigned)(k + 2)) : s1;
+        const int u1 = more ? cld(d.uoff, (unsigned)(k + 1)) : u0;
+        const int cnt1 = s2 - s1;
+        const int nt = tid < cnt1 * cnt1 ? cld(d.upd, (unsigned)(u1 + tid)) : 0;
+        const int nr = tid < cnt1 ? cld(d.sidx, (unsigned)(s1 + tid)) : 0;
+        if (cnt > 0) {
+          const double inv = 1.0 / val[k];
+          const double yk = rhs[k] * inv;
+          const double* lk = val + m + s0;
+          const double* uk = val + m + ns + s0;
+          const float rc = 1.0f / (float)cnt;
+          for (int t = tid; t < cnt * cnt; t += BLOCK) {
+            int ra = (int)(((float)t + 0.5f) * rc);  // t / cnt, corrected below
+            if (ra * cnt > t) --ra;
+            else if ((ra + 1) * cnt <= t) ++ra;
+            const int cb = t - ra * cnt;
+            const int tgt = t == tid ? pt : cld(d.upd, (unsigned)(u0 + t));
+            val[tgt] -= lk[ra] * inv * uk[cb];
+          }
+          for (int t = tid; t < cnt; t += BLOCK) {
+            const int r = t == tid ? pr : cld(d.sidx, (unsigned)(s0 + t));
+            rhs[r] -= lk[t] * yk;
+          }
+          __syncthreads();
+        }
+        s0 = s1;
+        s1 = s2;
+        u0 = u1;
+        cnt = cnt1;
+        pt = nt;
+        pr = nr;
+      }
+    }
+    // backward: U x = y by columns of U, x into xs; a thread's first entry of
+    // the next column is loaded while the current one computes
+    if (m > 0) {
+      int c1 = cld(d.ucp, (unsigned)m), c0 = cld(d.ucp, (unsigned)(m - 1));
+      int2 pu = c0 + tid < c1 ? cld(d.ucol, (unsigned)(c0 + tid)) : make_int2(0, 0);
+      for (int k = m - 1; k >= 0; --k) {
+        const int cm = k > 0 ? cld(d.ucp, (unsigned)(k - 1)) : c0;
+        const int2 nu = cm + tid < c0 ? cld(d.ucol, (unsigned)(cm + tid)) : make_int2(0, 0);
+        const double xk = rhs[k] / val[k];
+        if (tid == 0) xs[k] = xk;
+        if (c1 > c0) {
+          for (int t = c0 + tid; t < c1; t += BLOCK) {
+            const int2 u = t == c0 + tid ? pu : cld(d.ucol, (unsigned)t);
+            rhs[u.x] -= val[u.y] * xk;
+          }
+          __syncthreads();
+        }
+        c1 = c0;
+        c0 = cm;
+        pu = nu;
+      }
+    }
+    __syncthreads();
+    // Newton update (eq. (3)), own buses
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if ((int)i < nth) ws.st(TH, k, ws.ld(TH, k) + xs[cld(d.fpos, i)]);
+      if ((int)i < npq) ws.st(VM, k, ws.ld(VM, k) + xs[cld(d.fpos, (unsigned)NBP + i)]);
+    }
+    work += 8.0 * m + 32.0 * m;
+    ++newton;
+  }
+
+  const Buf vout = make_buf(a.v_out + 2 * (int64_t)b * a.ld);
+  {
+    const TxDev<double> net = load_desc(netp);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      if ((int)i < n) {
+        const unsigned e = (unsigned)cld(net.int2ext, i) * 16u;
+        double sn, cs;
+        sincos(ws.ld(TH, k), &sn, &cs);
+        const double vm = ws.ld(VM, k);
+        bst(vout, vm * cs, e, 0);
+        bst(vout, vm * sn, e, 8);
+      }
+    }
+  }
+  if (tid == 0) {
+    a.newton_iters[b] = newton;
+    if (a.gmres_iters) a.gmres_iters[b] = 0;
+    a.converged[b] = conv ? 1 : 0;
+    if (a.final_mismatch) a.final_mismatch[b] = fnorm;
+    if (a.work_bytes) a.work_bytes[b] = work;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint.  For w = [w_P on Theta ; w_Q on Q] and c = w_P + j w_Q (zero where
 // undefined), w^T dF = Re sum_k g_k dV_k with g = conj(c I) + Ybus^T (c conj V),
 // so (J^T w) = [-Im(g V) on Theta ; Re(g V) / |V| on Q].  Ends with a barrier.
@@ -1241,6 +1460,25 @@ struct NrGo {
   }
 };
 
+struct NrDirectGo {
+  const TxNetwork& net;
+  const NRLaunch& a;
+  hipStream_t s;
+  template <int BLOCK, int KB>
+  void operator()() const {
+    const DirectDev& d = net.direct;
+    const size_t lds = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
+    if (lds > 160 * 1024)
+      fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(lds) + " bytes of LDS)");
+    auto kernel = nr_direct_kernel<BLOCK, KB>;
+    if (lds > 64 * 1024)
+      PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kernel, dim3(a.batch), dim3(BLOCK), lds, s, net.desc<double>(), d, a);
+    PFX_HIP(hipGetLastError());
+  }
+};
+
 struct AdjGo {
   const TxNetwork& net;
   const AdjLaunch& a;
@@ -1298,6 +1536,12 @@ void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t 
   if (a.batch == 0) return;
   if (mixed) dispatch_shape(net.n, NrGo<float>{net, a, s});
   else dispatch_shape(net.n, NrGo<double>{net, a, s});
+}
+
+void launch_nr_direct(const TxNetwork& net, const NRLaunch& a, hipStream_t s) {
+  if (a.batch == 0) return;
+  if (!net.direct_ready) fail(PF_INVALID_ARG, "direct Newton step used before its analysis was built");
+  dispatch_shape(net.n, NrDirectGo{net, a, s});
 }
 
 void launch_adjoint(const TxNetwork& net, const AdjLaunch& a, hipStream_t s) {

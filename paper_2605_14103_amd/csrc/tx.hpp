@@ -67,6 +67,19 @@ struct TxDev {
   const double* br_b;
 };
 
+// Device view of the direct Newton step's shared analysis (direct.hpp).
+struct DirectDev {
+  int m, n_s, n_val, n_je;
+  const int* fpos;   // [2 nbp]
+  const int* soff;   // [m + 1]
+  const int* sidx;
+  const int* uoff;   // [m + 1]
+  const int* upd;
+  const int* ucp;    // [m + 1]
+  const int2* ucol;  // (row, value index)
+  const int4* je;    // (value index | kind << 28, bus i, bus k, Ybus layout index)
+};
+
 struct EfBuffers {
   ExplicitFactor host;
   bool direct = false;
@@ -94,6 +107,14 @@ struct TxNetwork {
   int caller_nnz = 0;
   int64_t y_entries = 0;
   DeviceBuffer ysrc_ptr, ysrc_idx;
+  // internal Ybus pattern (rows by internal bus, sorted columns) and the
+  // layout entry of each internal entry
+  std::vector<int> y_ptr, y_col, y_pos;
+  // direct Newton step: analysis built on first use
+  bool direct_ready = false;
+  int direct_nval = 0;
+  DirectDev direct{};
+  DeviceBuffer dl_fpos, dl_soff, dl_sidx, dl_uoff, dl_upd, dl_ucp, dl_ucol, dl_je;
   // solve workspaces (grow-only); calls on one network must not overlap
   DeviceBuffer ws_d, ws_basis, ws_adj, ws_y;
   // the device views themselves, resident in device memory so kernels take one pointer
@@ -150,6 +171,9 @@ void launch_y_gather(const TxNetwork& net, int batch, int64_t ldy, const double*
 int64_t nr_ws_doubles(const TxNetwork& net);
 int64_t nr_padded_rows(const TxNetwork& net);
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s);
+// Direct Newton step (FP64), after ensure_direct(net).
+void ensure_direct(TxNetwork& net);
+void launch_nr_direct(const TxNetwork& net, const NRLaunch& a, hipStream_t s);
 
 struct LossLaunch {
   int batch;

@@ -9,6 +9,7 @@
 #include <string>
 #include <tuple>
 
+#include "direct.hpp"
 #include "tx.hpp"
 
 namespace pfx {
@@ -343,6 +344,11 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
         src[q].push_back(p);
       }
     }
+    net->y_ptr = ptr;
+    net->y_col = col;
+    net->y_pos.assign(col.size(), 0);
+    for (int i = 0; i < n_bus; ++i)
+      for (int p = ptr[i]; p < ptr[i + 1]; ++p) net->y_pos[p] = hy.off[i / 64] + (p - ptr[i]) * 64 + i % 64;
     std::vector<int> sp(E + 1, 0), si;
     for (int64_t q = 0; q < E; ++q) {
       si.insert(si.end(), src[q].begin(), src[q].end());
@@ -398,6 +404,40 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
   net->desc64 = upload(ctx, std::vector<TxDev<double>>{net->view<double>()});
   net->desc32 = upload(ctx, std::vector<TxDev<float>>{net->view<float>()});
   return net.release();
+}
+
+}  // namespace pfx
+
+namespace pfx {
+
+void ensure_direct(TxNetwork& net) {
+  if (net.direct_ready) return;
+  const DirectLuHost D = build_direct_lu(net);
+  Context* ctx = net.ctx;
+  auto up = [&](const std::vector<int>& v) { return upload(ctx, v.empty() ? std::vector<int>{0} : v); };
+  net.dl_fpos = up(D.fpos);
+  net.dl_soff = up(D.soff);
+  net.dl_sidx = up(D.sidx);
+  net.dl_uoff = up(D.uoff);
+  net.dl_upd = up(D.upd);
+  net.dl_ucp = up(D.ucp);
+  net.dl_ucol = up(D.ucol.empty() ? std::vector<int>{0, 0} : D.ucol);
+  net.dl_je = up(D.je.empty() ? std::vector<int>{0, 0, 0, 0} : D.je);
+  DirectDev& d = net.direct;
+  d.m = D.m;
+  d.n_s = D.n_s;
+  d.n_val = D.n_val;
+  d.n_je = (int)D.je.size() / 4;
+  d.fpos = net.dl_fpos.as<int>();
+  d.soff = net.dl_soff.as<int>();
+  d.sidx = net.dl_sidx.as<int>();
+  d.uoff = net.dl_uoff.as<int>();
+  d.upd = net.dl_upd.as<int>();
+  d.ucp = net.dl_ucp.as<int>();
+  d.ucol = net.dl_ucol.as<int2>();
+  d.je = net.dl_je.as<int4>();
+  net.direct_nval = D.n_val;
+  net.direct_ready = true;
 }
 
 }  // namespace pfx

@@ -380,3 +380,70 @@ def test_yvals_argument_errors(ctx):
                                       None, None, None, None, None, None, None)
     assert st == _lib.PF_INVALID_ARG
     net.close()
+
+
+def _grid_cfg(n_bus):
+    if n_bus == 30:
+        return tx.TX30
+    return tx.TxConfig(f"tx{n_bus}", n_bus=n_bus, n_pv=max(5, n_bus * 15 // 100), n_branch=int(n_bus * 1.3),
+                       batch=48, seed=n_bus, perturbation="uniform", spread=0.2)
+
+
+@pytest.mark.parametrize("n_bus", [30, 118, 500])
+def test_direct_newton_matches_oracle_step_for_step(ctx, n_bus):
+    """The direct Newton step (per-scenario sparse LU on the shared analysis)
+    takes exact Newton steps, as the oracle does: every scenario agrees with the
+    oracle in V and takes the same number of Newton updates."""
+    from paper_2605_14103_amd import pf
+    cfg = _grid_cfg(n_bus)
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    res = _solve(net, batch, nr_direct=1)
+    V, it, ok, mm = onr.nr_solve_batch(grid, batch)
+    v = res.v.cpu().numpy()
+    da, dm = angle_err(v, V)
+    nit = res.newton_iters.cpu().numpy()
+    say(f"{cfg.name} direct: max angle err {da:.2e}, max |V| err {dm:.2e}, newton {nit.tolist()[:8]} "
+        f"(oracle {it.tolist()[:8]}), mismatch max {res.mismatch.cpu().numpy().max():.2e}")
+    assert ok.all() and res.converged.cpu().numpy().all()
+    assert res.mismatch.cpu().numpy().max() <= 1e-8
+    assert da <= TOL_A and dm <= TOL_V
+    np.testing.assert_array_equal(nit, it)
+    assert (res.gmres_iters.cpu().numpy() == 0).all()
+    net.close()
+
+
+def test_direct_newton_with_branch_outages(ctx):
+    """The direct step with per-scenario admittance values: the 30-bus grid with
+    two branches out per scenario against the oracle (same Newton updates)."""
+    import torch
+    from paper_2605_14103_amd import pf
+    grid = tx.make_grid(tx.TX30)
+    batch = tx.make_batch(grid, tx.TX30)
+    on = tx.make_outages(grid, batch.batch, n_out=2, seed=37)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    yv = torch.from_numpy(net.ybus_switch(on)).cuda()
+    res = _solve_yvals(net, batch, yv, nr_direct=1)
+    _check_outages(grid, batch, on, res, np.arange(batch.batch), "tx30 direct, 2 out")
+    nit = res.newton_iters.cpu().numpy()
+    for c in range(batch.batch):
+        m = on[c].astype(bool)
+        Y = onr.ybus(grid.n_bus, grid.f[m], grid.t[m], grid.r[m], grid.x[m], grid.b[m])
+        ref = onr.nr_solve(Y, grid.bus_type, batch.p_inj[c], batch.q_inj[c], batch.vm_set[c])
+        assert nit[c] == ref.iters
+    net.close()
+
+
+def test_direct_newton_refuses_a_network_too_large(ctx):
+    from paper_2605_14103_amd import _lib, pf
+    grid = tx.make_grid(tx.TX2000)
+    batch = tx.make_batch(grid, tx.TX2000, batch=2)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    with pytest.raises(_lib.PfError) as e:
+        _solve(net, batch, nr_direct=1)
+    assert e.value.status == _lib.PF_INVALID_ARG and "factor values" in str(e.value)
+    # the GMRES path still works on the same network afterwards
+    res = _solve(net, batch)
+    assert res.converged.cpu().numpy().all()
+    net.close()
