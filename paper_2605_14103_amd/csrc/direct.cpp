@@ -2,6 +2,7 @@
 #include "direct.hpp"
 
 #include <algorithm>
+#include <map>
 #include <set>
 #include <string>
 
@@ -81,22 +82,45 @@ DirectLuHost build_direct_lu(const TxNetwork& net) {
     if (at == e || *at != r) fail(PF_SINGULAR_SETUP, "entry outside the symbolic pattern of the Jacobian");
     return (i > j ? m : m + D.n_s) + D.soff[c] + (int)(at - b);
   };
-  D.uoff.assign(m + 1, 0);
+  // elimination-tree levels: the parent of k is the first entry of S(k)
+  std::vector<int> lf(m, 0), lb(m, 0);
+  for (int k = 0; k < m; ++k)
+    if (D.soff[k + 1] > D.soff[k]) lf[D.sidx[D.soff[k]]] = std::max(lf[D.sidx[D.soff[k]]], lf[k] + 1);
+  for (int k = m - 1; k >= 0; --k)
+    for (int q = D.soff[k]; q < D.soff[k + 1]; ++q) lb[k] = std::max(lb[k], lb[D.sidx[q]] + 1);
+  const int nf = m ? *std::max_element(lf.begin(), lf.end()) + 1 : 0;
+  const int nb = m ? *std::max_element(lb.begin(), lb.end()) + 1 : 0;
+  std::vector<std::vector<int>> by_f(nf), by_b(nb);
   for (int k = 0; k < m; ++k) {
-    for (int q = D.soff[k]; q < D.soff[k + 1]; ++q)
-      for (int r = D.soff[k]; r < D.soff[k + 1]; ++r) D.upd.push_back(pos(D.sidx[q], D.sidx[r]));
-    D.uoff[k + 1] = (int)D.upd.size();
+    by_f[lf[k]].push_back(k);
+    by_b[lb[k]].push_back(k);
   }
-  std::vector<std::vector<int>> uc(m);
-  for (int i = 0; i < m; ++i)
-    for (int q = D.soff[i]; q < D.soff[i + 1]; ++q) uc[D.sidx[q]].push_back(i);
-  D.ucp.assign(m + 1, 0);
-  for (int k = 0; k < m; ++k) {
-    for (int i : uc[k]) {
-      D.ucol.push_back(i);
-      D.ucol.push_back(pos(i, k));
+  D.fph.assign(1, 0);
+  for (int f = 0; f < nf; ++f) {
+    // key: value index for matrix targets, -1 - row for right-hand-side targets
+    std::map<int, std::vector<int>> contrib;
+    for (int k : by_f[f]) {
+      const int s0 = D.soff[k], cnt = D.soff[k + 1] - s0;
+      for (int x = 0; x < cnt; ++x) {
+        for (int y = 0; y < cnt; ++y) {
+          auto& c = contrib[pos(D.sidx[s0 + x], D.sidx[s0 + y])];
+          c.insert(c.end(), {m + s0 + x, m + D.n_s + s0 + y, k, 0});
+        }
+        auto& c = contrib[-1 - D.sidx[s0 + x]];
+        c.insert(c.end(), {m + s0 + x, k, k, 0});
+      }
     }
-    D.ucp[k + 1] = (int)D.ucol.size() / 2;
+    for (auto& [key, c] : contrib) {
+      const int first = (int)D.fct.size() / 4;
+      D.fct.insert(D.fct.end(), c.begin(), c.end());
+      D.ftg.insert(D.ftg.end(), {key >= 0 ? key : -1 - key, first, (int)D.fct.size() / 4, key >= 0 ? 0 : 1});
+    }
+    D.fph.push_back((int)D.ftg.size() / 4);
+  }
+  D.bph.assign(1, 0);
+  for (int l = 0; l < nb; ++l) {
+    D.brow.insert(D.brow.end(), by_b[l].begin(), by_b[l].end());
+    D.bph.push_back((int)D.brow.size());
   }
   D.fpos.assign(2 * nbp, -1);
   for (int s = 0; s < m; ++s) D.fpos[s < nth ? s : nbp + (s - nth)] = pinv[s];

@@ -23,10 +23,18 @@ struct DirectLuHost {
   std::vector<int> fpos;     // [2 nbp]: factor position of theta_i (i) and |V|_i (nbp + i), -1 if none
   std::vector<int> soff;     // [m + 1]: S(k) = sidx[soff[k] .. soff[k + 1])
   std::vector<int> sidx;
-  std::vector<int> uoff;     // [m + 1]: updates of pivot k, pairs (a, b) of S(k) x S(k), a-major
-  std::vector<int> upd;      // value index of entry (S_a, S_b)
-  std::vector<int> ucp;      // [m + 1]: column k of U above the diagonal
-  std::vector<int> ucol;     // pairs (row, value index)
+  // Factorisation (with the forward solve) by levels of the elimination
+  // tree: pivots of one level are never ancestor and descendant, so none
+  // changes another's row, column or right-hand-side entry.  Phase f lists
+  // its targets ftg[fph[f] .. fph[f + 1]) (4 ints: value or right-hand-side
+  // index, first and end contribution, 1 for a right-hand-side target); a
+  // target takes all its contributions of the phase, in pivot order, from
+  // fct (4 ints: L entry, U entry or right-hand-side index of the pivot, the
+  // pivot, 0): target -= L[i][k] x / U[k][k].
+  std::vector<int> fph, ftg, fct;
+  // Backward solve by levels: phase b computes x_k for the rows
+  // brow[bph[b] .. bph[b + 1]), whose U entries reference solved rows only.
+  std::vector<int> bph, brow;
   std::vector<int> je;       // J entries, 4 ints each: (value index | kind << 28, bus i, bus k, Ybus layout index)
 };
 

@@ -983,10 +983,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // Direct Newton step (FP64): per scenario, the Jacobian of eq. (4) is formed
 // in the shared fill pattern (direct.hpp), factorised by LU without pivoting
 // in the shared minimum-degree order and solved by the two triangular
-// solves; one workgroup per scenario with the factor in LDS.  The pivots run
-// in order; within a pivot, its rank-one update of the trailing entries
-// (distinct targets) is spread over the workgroup, as are the entries of each
-// backward-solve step; the forward solve runs inside the factorisation.
+// solves; one workgroup per scenario with the factor in LDS.  Both the
+// factorisation (with the forward solve inside it) and the backward solve run
+// one phase per level of the elimination tree, with the phase's targets
+// (rows) spread over the workgroup.
 //
 // Entries of J for a Ybus entry (i, k), with a = V_i conj(Y_ik V_k) and
 // c = V_i conj(I_i) (the bus power):  i != k: dS_i/dtheta_k = -j a,
@@ -1092,76 +1092,39 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
       }
     }
     __syncthreads();
-    // LU in factor order with the forward solve L y = -F fused in: L[S(k), k]
-    // stays unscaled (its entries hold L U[k][k]) and is divided by the pivot
-    // where used, so each pivot is one phase: the rank-one update of its
-    // trailing entries (distinct targets) and the update of rhs[S(k)] read
-    // only pivot k's own row, column and rhs[k], all final after the barrier
-    // that closed the previous pivot.  A thread's first update target and row
-    // index of the next pivot are loaded while the current pivot computes.
-    if (m > 0) {  // (m = 0 converges at the first mismatch; kept for clarity)
-      int s0 = cld(d.soff, 0u), s1 = cld(d.soff, 1u), u0 = cld(d.uoff, 0u);
-      int cnt = s1 - s0;
-      int pt = tid < cnt * cnt ? cld(d.upd, (unsigned)(u0 + tid)) : 0;
-      int pr = tid < cnt ? cld(d.sidx, (unsigned)(s0 + tid)) : 0;
-      for (int k = 0; k < m; ++k) {
-        const bool more = k + 1 < m;
-        const int s2 = more ? cld(d.soff, (unsigned)(k + 2)) : s1;
-        const int u1 = more ? cld(d.uoff, (unsigned)(k + 1)) : u0;
-        const int cnt1 = s2 - s1;
-        const int nt = tid < cnt1 * cnt1 ? cld(d.upd, (unsigned)(u1 + tid)) : 0;
-        const int nr = tid < cnt1 ? cld(d.sidx, (unsigned)(s1 + tid)) : 0;
-        if (cnt > 0) {
-          const double inv = 1.0 / val[k];
-          const double yk = rhs[k] * inv;
-          const double* lk = val + m + s0;
-          const double* uk = val + m + ns + s0;
-          const float rc = 1.0f / (float)cnt;
-          for (int t = tid; t < cnt * cnt; t += BLOCK) {
-            int ra = (int)(((float)t + 0.5f) * rc);  // t / cnt, corrected below
-            if (ra * cnt > t) --ra;
-            else if ((ra + 1) * cnt <= t) ++ra;
-            const int cb = t - ra * cnt;
-            const int tgt = t == tid ? pt : cld(d.upd, (unsigned)(u0 + t));
-            val[tgt] -= lk[ra] * inv * uk[cb];
-          }
-          for (int t = tid; t < cnt; t += BLOCK) {
-            const int r = t == tid ? pr : cld(d.sidx, (unsigned)(s0 + t));
-            rhs[r] -= lk[t] * yk;
-          }
-          __syncthreads();
+    // LU with the forward solve L y = -F fused in, by levels of the
+    // elimination tree: one phase per level, one thread per target, which
+    // subtracts L[i][k] x / U[k][k] for each of its contributions (pivots of
+    // the level, in pivot order; x the U entry or rhs[k]).  Pivots of a level
+    // read only their own row, column and rhs entry, which no pivot of the
+    // level changes, and L stays unscaled (its entries hold L U[k][k]).
+    for (int ph = 0; ph < d.n_fph; ++ph) {
+      const int q1 = cld(d.fph, (unsigned)(ph + 1));
+      for (int q = cld(d.fph, (unsigned)ph) + tid; q < q1; q += BLOCK) {
+        const int4 T = cld(d.ftg, (unsigned)q);
+        double acc = 0.0;
+        for (int c = T.y; c < T.z; ++c) {
+          const int4 C = cld(d.fct, (unsigned)c);
+          acc += val[C.x] * (T.w ? rhs[C.y] : val[C.y]) / val[C.z];
         }
-        s0 = s1;
-        s1 = s2;
-        u0 = u1;
-        cnt = cnt1;
-        pt = nt;
-        pr = nr;
+        if (T.w) rhs[T.x] -= acc;
+        else val[T.x] -= acc;
       }
+      __syncthreads();
     }
-    // backward: U x = y by columns of U, x into xs; a thread's first entry of
-    // the next column is loaded while the current one computes
-    if (m > 0) {
-      int c1 = cld(d.ucp, (unsigned)m), c0 = cld(d.ucp, (unsigned)(m - 1));
-      int2 pu = c0 + tid < c1 ? cld(d.ucol, (unsigned)(c0 + tid)) : make_int2(0, 0);
-      for (int k = m - 1; k >= 0; --k) {
-        const int cm = k > 0 ? cld(d.ucp, (unsigned)(k - 1)) : c0;
-        const int2 nu = cm + tid < c0 ? cld(d.ucol, (unsigned)(cm + tid)) : make_int2(0, 0);
-        const double xk = rhs[k] / val[k];
-        if (tid == 0) xs[k] = xk;
-        if (c1 > c0) {
-          for (int t = c0 + tid; t < c1; t += BLOCK) {
-            const int2 u = t == c0 + tid ? pu : cld(d.ucol, (unsigned)t);
-            rhs[u.x] -= val[u.y] * xk;
-          }
-          __syncthreads();
-        }
-        c1 = c0;
-        c0 = cm;
-        pu = nu;
+    // backward: U x = y by levels, one thread per row: x_k = (y_k - U[k][S(k)]
+    // x[S(k)]) / U[k][k], the x it reads solved in earlier levels
+    for (int ph = 0; ph < d.n_bph; ++ph) {
+      const int q1 = cld(d.bph, (unsigned)(ph + 1));
+      for (int q = cld(d.bph, (unsigned)ph) + tid; q < q1; q += BLOCK) {
+        const int k = cld(d.brow, (unsigned)q);
+        const int s1 = cld(d.soff, (unsigned)(k + 1));
+        double acc = rhs[k];
+        for (int t = cld(d.soff, (unsigned)k); t < s1; ++t) acc -= val[m + ns + t] * xs[cld(d.sidx, (unsigned)t)];
+        xs[k] = acc / val[k];
       }
+      __syncthreads();
     }
-    __syncthreads();
     // Newton update (eq. (3)), own buses
 #pragma unroll
     for (int k = 0; k < KB; ++k) {

@@ -69,14 +69,15 @@ struct TxDev {
 
 // Device view of the direct Newton step's shared analysis (direct.hpp).
 struct DirectDev {
-  int m, n_s, n_val, n_je;
+  int m, n_s, n_val, n_je, n_fph, n_bph;
   const int* fpos;   // [2 nbp]
   const int* soff;   // [m + 1]
   const int* sidx;
-  const int* uoff;   // [m + 1]
-  const int* upd;
-  const int* ucp;    // [m + 1]
-  const int2* ucol;  // (row, value index)
+  const int* fph;    // [n_fph + 1]
+  const int4* ftg;   // (target, first contribution, end, 1 for a right-hand-side target)
+  const int4* fct;   // (L entry, U entry or right-hand-side index, pivot, 0)
+  const int* bph;    // [n_bph + 1]
+  const int* brow;
   const int4* je;    // (value index | kind << 28, bus i, bus k, Ybus layout index)
 };
 
@@ -114,7 +115,7 @@ struct TxNetwork {
   bool direct_ready = false;
   int direct_nval = 0;
   DirectDev direct{};
-  DeviceBuffer dl_fpos, dl_soff, dl_sidx, dl_uoff, dl_upd, dl_ucp, dl_ucol, dl_je;
+  DeviceBuffer dl_fpos, dl_soff, dl_sidx, dl_fph, dl_ftg, dl_fct, dl_bph, dl_brow, dl_je;
   // solve workspaces (grow-only); calls on one network must not overlap
   DeviceBuffer ws_d, ws_basis, ws_adj, ws_y;
   // the device views themselves, resident in device memory so kernels take one pointer

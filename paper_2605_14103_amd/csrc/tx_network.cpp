@@ -418,23 +418,27 @@ void ensure_direct(TxNetwork& net) {
   net.dl_fpos = up(D.fpos);
   net.dl_soff = up(D.soff);
   net.dl_sidx = up(D.sidx);
-  net.dl_uoff = up(D.uoff);
-  net.dl_upd = up(D.upd);
-  net.dl_ucp = up(D.ucp);
-  net.dl_ucol = up(D.ucol.empty() ? std::vector<int>{0, 0} : D.ucol);
+  net.dl_fph = up(D.fph);
+  net.dl_ftg = up(D.ftg.empty() ? std::vector<int>{0, 0, 0, 0} : D.ftg);
+  net.dl_fct = up(D.fct.empty() ? std::vector<int>{0, 0, 0, 0} : D.fct);
+  net.dl_bph = up(D.bph);
+  net.dl_brow = up(D.brow);
   net.dl_je = up(D.je.empty() ? std::vector<int>{0, 0, 0, 0} : D.je);
   DirectDev& d = net.direct;
   d.m = D.m;
   d.n_s = D.n_s;
   d.n_val = D.n_val;
   d.n_je = (int)D.je.size() / 4;
+  d.n_fph = (int)D.fph.size() - 1;
+  d.n_bph = (int)D.bph.size() - 1;
   d.fpos = net.dl_fpos.as<int>();
   d.soff = net.dl_soff.as<int>();
   d.sidx = net.dl_sidx.as<int>();
-  d.uoff = net.dl_uoff.as<int>();
-  d.upd = net.dl_upd.as<int>();
-  d.ucp = net.dl_ucp.as<int>();
-  d.ucol = net.dl_ucol.as<int2>();
+  d.fph = net.dl_fph.as<int>();
+  d.ftg = net.dl_ftg.as<int4>();
+  d.fct = net.dl_fct.as<int4>();
+  d.bph = net.dl_bph.as<int>();
+  d.brow = net.dl_brow.as<int>();
   d.je = net.dl_je.as<int4>();
   net.direct_nval = D.n_val;
   net.direct_ready = true;
