@@ -163,6 +163,14 @@ __device__ __forceinline__ float2 cld(const float2* base, unsigned i) {
   return r;
 }
 
+// For a kernel whose workgroup is a single wavefront and whose lanes exchange
+// data through LDS only: waits for the wavefront's own LDS operations, so
+// its later LDS reads see every lane's earlier writes, without the wait for
+// outstanding global loads that __syncthreads() implies (a workgroup-scope
+// fence), which would stall on loads issued ahead for the next step.  The
+// memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // Compiler-only fence between the bus slots of an unrolled loop: keeps the
 // loads of later slots from being hoisted above earlier ones, which would hold
 // every slot's operands in registers at once.

@@ -369,44 +369,49 @@ __device__ __forceinline__ void zf_solve(typename Vec2<T>::type* u, int nq, cons
       acc.y -= c[t].x * z.y + c[t].y * z.x;
     }
   };
-  int4 m = cld(meta, 0u);
-  int i = cld(row, (unsigned)lane);
-  T2 c[4], d;
-  int j[4];
-  round(m.x, c, j);
-  if (BACK) d = cld(dinv, (unsigned)lane);
-  for (int q = 0; q < nq; ++q) {
-    const int qn = q + 1 < nq ? q + 1 : q;  // the last slice re-reads itself
-    const int4 mn = cld(meta, (unsigned)qn);
-    const int in = cld(row, (unsigned)(qn * WAVE + lane));
-    T2 cn[4], dn;
-    int jn[4];
-    round(mn.x, cn, jn);
-    if (BACK) dn = cld(dinv, (unsigned)(qn * WAVE + lane));
-    const T2 z = u[i < 0 ? 0 : i];
+  // One slice's descriptor, row id, first round of entries and 1 / D.  Two
+  // of them alternate (the loop is unrolled by two), so a slice's loads stay
+  // in flight while the previous slice computes and no register copy at the
+  // loop's back edge waits for them.
+  struct Slot {
+    int4 m;
+    int i;
+    T2 c[4], d;
+    int j[4];
+  };
+  auto load = [&](int q, Slot& S) {
+    S.m = cld(meta, (unsigned)q);
+    S.i = cld(row, (unsigned)(q * WAVE + lane));
+    round(S.m.x, S.c, S.j);
+    if (BACK) S.d = cld(dinv, (unsigned)(q * WAVE + lane));
+  };
+  auto run = [&](const Slot& S) {
+    const T2 z = u[S.i < 0 ? 0 : S.i];
     T2 acc = z;
     if (BACK) {
-      acc.x = z.x * d.x - z.y * d.y;
-      acc.y = z.x * d.y + z.y * d.x;
+      acc.x = z.x * S.d.x - z.y * S.d.y;
+      acc.y = z.x * S.d.y + z.y * S.d.x;
     }
-    apply(c, j, acc);
-    for (int e = 4; e < m.y; e += 4) {
+    apply(S.c, S.j, acc);
+    for (int e = 4; e < S.m.y; e += 4) {
       T2 c2[4];
       int j2[4];
-      round(m.x + e * WAVE, c2, j2);
+      round(S.m.x + e * WAVE, c2, j2);
       apply(c2, j2, acc);
     }
-    if (i >= 0) u[i] = acc;
-    if (m.z) __syncthreads();
-    m = mn;
-    i = in;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      c[t] = cn[t];
-      j[t] = jn[t];
-    }
-    if (BACK) d = dn;
+    if (S.i >= 0) u[S.i] = acc;
+    if (S.m.z) wave_lds_sync();  // one wavefront per workgroup (see zb_sparse)
+  };
+  Slot A, B;
+  load(0, A);
+  int q = 0;
+  for (; q + 1 < nq; q += 2) {
+    load(q + 1, B);
+    run(A);
+    load(q + 2 < nq ? q + 2 : q + 1, A);  // the last pair re-reads a slice it holds
+    run(B);
   }
+  if (q < nq) run(A);
 }
 
 // Sparse variant of the update: v += Y_NN^-1 r by the L D L^T factor of
