@@ -330,6 +330,45 @@ def bench_tx_switch(steps: int, warmup: int) -> dict:
             "runs": runs}
 
 
+def bench_direct_sizes(steps: int, warmup: int) -> dict:
+    """Newton linear solver against grid size: preconditioned GMRES (FP64 and
+    mixed) against the direct step (per-scenario sparse LU, FP64), batch 64
+    and 1024, grids of 30 to 500 buses."""
+    import torch
+
+    from paper_2605_14103_amd import pf
+    from workloads import transmission as tx
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    rows = []
+    ctx = pf.Context(0)
+    for n_bus in (30, 118, 300, 500):
+        cfg = tx.TX30 if n_bus == 30 else tx.TxConfig(
+            f"tx{n_bus}", n_bus=n_bus, n_pv=max(5, n_bus * 15 // 100), n_branch=int(n_bus * 1.3), batch=64,
+            seed=n_bus, perturbation="uniform", spread=0.2)
+        grid = tx.make_grid(cfg)
+        net = pf.TxNetwork.from_grid(ctx, grid)
+        for B in (64, 1024):
+            batch = tx.make_batch(grid, cfg, batch=B)
+            p, q, vm = dev(batch.p_inj), dev(batch.q_inj), dev(batch.vm_set)
+            for kind, opts in (("gmres_fp64", {}), ("gmres_mixed", {"precision": pf.precision("mixed")}),
+                               ("direct", {"nr_direct": 1})):
+                out = net.solve(p, q, vm, **opts)
+                ms, _, out = time_steps(lambda: net.solve(p, q, vm, out=out, **opts), steps, warmup)
+                conv = int(out.converged.sum().item())
+                rows.append({"n_bus": n_bus, "batch": B, "solver": kind, "ms": float(ms.mean()),
+                             "solves_per_s": conv / (float(ms.mean()) * 1e-3), "converged": conv,
+                             "newton_iters_mean": float(out.newton_iters.double().mean().item())})
+                print(f"[direct] tx{n_bus} B={B} {kind} {ms.mean():.3f} ms", file=sys.stderr, flush=True)
+        net.close()
+    ctx.close()
+    best = max(r["solves_per_s"] for r in rows if r["n_bus"] == 30)
+    return {"metric": METRIC, "value": best, "unit": "solves/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "Newton linear solver sweep: GMRES against the direct step, 30-500 buses"},
+            "sizes": rows}
+
+
 def bench_feeder_sizes(steps: int, warmup: int) -> dict:
     """Dense Z product against the sparse Y_NN factor as the feeder grows (batch 1024, both precisions)."""
     import torch
@@ -559,7 +598,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="tx2000",
                     choices=["tx2000", "tx30", "feeder", "adjoint", "serving", "sweep", "feeder_sizes",
-                             "tx2000_switch"])
+                             "tx2000_switch", "direct_sizes"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--streams", default="1,2,1",
@@ -593,6 +632,8 @@ def main() -> int:
         line = bench_feeder_sizes(a.steps, a.warmup)
     elif a.workload == "tx2000_switch":
         line = bench_tx_switch(a.steps, a.warmup)
+    elif a.workload == "direct_sizes":
+        line = bench_direct_sizes(a.steps, a.warmup)
     else:
         line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
     print(json.dumps(line), flush=True)
