@@ -78,12 +78,13 @@ def test_tx2000_full_batch_sampled(ctx, precision):
     net.close()
 
 
-def test_two_bus_closed_form(ctx):
+@pytest.mark.parametrize("direct", [0, 1])
+def test_two_bus_closed_form(ctx, direct):
     from paper_2605_14103_amd import pf
     from tests.test_oracle_nr import two_bus_closed_form
     grid, batch = tx.two_bus(0.03, 0.12, 0.8, 0.25, batch=3)
     net = pf.TxNetwork.from_grid(ctx, grid)
-    res = _solve(net, batch, tol=1e-12)
+    res = _solve(net, batch, tol=1e-12, nr_direct=direct)
     vm, th = two_bus_closed_form(0.03, 0.12, 0.8, 0.25)
     v = res.v.cpu().numpy()
     assert res.converged.cpu().numpy().all()
@@ -92,12 +93,13 @@ def test_two_bus_closed_form(ctx):
     net.close()
 
 
-def test_zero_load_takes_no_iteration(ctx):
+@pytest.mark.parametrize("direct", [0, 1])
+def test_zero_load_takes_no_iteration(ctx, direct):
     from paper_2605_14103_amd import pf
     grid = tx.make_grid(tx.TX30)
     grid.b = np.zeros_like(grid.b)
     net = pf.TxNetwork.from_grid(ctx, grid)
-    res = _solve(net, tx.zero_load(grid, batch=2))
+    res = _solve(net, tx.zero_load(grid, batch=2), nr_direct=direct)
     assert res.converged.cpu().numpy().all()
     assert (res.newton_iters.cpu().numpy() == 0).all()
     np.testing.assert_array_equal(res.v.cpu().numpy(), np.ones((2, grid.n_bus)))
@@ -446,4 +448,35 @@ def test_direct_newton_refuses_a_network_too_large(ctx):
     # the GMRES path still works on the same network afterwards
     res = _solve(net, batch)
     assert res.converged.cpu().numpy().all()
+    net.close()
+
+
+def test_direct_edge_cases_and_isolation(ctx):
+    """The direct step: empty batch, an infeasible and a NaN scenario next to
+    good ones (the good ones bitwise unaffected), an iteration cap of one."""
+    import torch
+    from paper_2605_14103_amd import pf
+    grid = tx.make_grid(tx.TX30)
+    batch = tx.make_batch(grid, tx.TX30, batch=5)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    ref = _solve(net, batch, nr_direct=1)
+    e = torch.zeros((0, grid.n_bus), dtype=torch.float64, device="cuda")
+    assert net.solve(e, e, e, nr_direct=1).v.shape == (0, grid.n_bus)
+    p = batch.p_inj.copy()
+    q = batch.q_inj.copy()
+    p[1] *= 50
+    q[1] *= 50
+    p[3, 4] = np.nan
+    bad = net.solve(to_dev(p), to_dev(q), to_dev(batch.vm_set), nr_direct=1)
+    torch.cuda.synchronize()
+    conv = bad.converged.cpu().numpy()
+    assert conv[1] == 0 and conv[3] == 0 and conv[[0, 2, 4]].all()
+    for c in (0, 2, 4):
+        assert torch.equal(bad.v[c], ref.v[c])
+    capped = _solve(net, batch, max_newton=1, nr_direct=1)
+    assert not capped.converged.cpu().numpy().any()
+    assert (capped.newton_iters.cpu().numpy() == 1).all()
+    # the direct step ignores the precision option (always FP64): same result
+    mixed = _solve(net, batch, nr_direct=1, precision=pf.precision("mixed"))
+    assert torch.equal(mixed.v, ref.v)
     net.close()

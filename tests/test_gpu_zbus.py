@@ -70,14 +70,15 @@ def test_feeder300_full_batch_sampled(ctx, precision):
     net.close()
 
 
+@pytest.mark.parametrize("sparse", [0, 1])
 @pytest.mark.parametrize("kind", [1, 2])
-def test_balanced_segment_closed_form(ctx, kind):
+def test_balanced_segment_closed_form(ctx, kind, sparse):
     from paper_2605_14103_amd import pf
     from tests.test_oracle_zbus import _closed_form_phase_a
     z_self, kappa, s = 0.03 + 0.06j, 0.4, 2.0 + 0.7j
     fd, batch = fdm.single_segment(z_self, kappa, kind, s, batch=2)
     net = pf.DistNetwork.from_feeder(ctx, fd)
-    res = _solve(net, batch, tol=1e-12)
+    res = _solve(net, batch, tol=1e-12, zbus_sparse=sparse)
     va = _closed_form_phase_a(z_self * (1 - kappa), s)
     a = np.exp(-2j * np.pi / 3)
     v = res.v.cpu().numpy()
@@ -86,21 +87,22 @@ def test_balanced_segment_closed_form(ctx, kind):
     net.close()
 
 
-def test_zero_load_and_caps(ctx):
+@pytest.mark.parametrize("sparse", [0, 1])
+def test_zero_load_and_caps(ctx, sparse):
     from paper_2605_14103_amd import pf
     cfg = fdm.FeederConfig("feeder40", n_bus=40, max_depth=25, batch=3, seed=41)
     fd = fdm.make_feeder(cfg)
     net = pf.DistNetwork.from_feeder(ctx, fd)
-    res = _solve(net, fdm.zero_load(fd, 3))
+    res = _solve(net, fdm.zero_load(fd, 3), zbus_sparse=sparse)
     assert res.converged.cpu().numpy().all() and (res.iters.cpu().numpy() == 0).all()
     np.testing.assert_allclose(res.v.cpu().numpy(), np.tile(fd.v_slack, (3, fd.n_bus)), atol=1e-13)
     batch = fdm.make_batch(fd, cfg)
-    capped = _solve(net, batch, zbus_max_iter=1)
+    capped = _solve(net, batch, zbus_max_iter=1, zbus_sparse=sparse)
     assert not capped.converged.cpu().numpy().any() and (capped.iters.cpu().numpy() == 1).all()
     bad = fdm.FeederBatch(batch.s_wye.copy(), batch.s_delta.copy())
     bad.s_wye[1, 5] = np.nan
-    r2 = _solve(net, bad)
-    full = _solve(net, batch)
+    r2 = _solve(net, bad, zbus_sparse=sparse)
+    full = _solve(net, batch, zbus_sparse=sparse)
     c = r2.converged.cpu().numpy()
     assert c[0] and c[2] and not c[1]
     import torch
