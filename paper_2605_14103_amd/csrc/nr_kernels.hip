@@ -993,7 +993,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 // dS_i/d|V_k| = a / |V_k|;  i == k: dS_i/dtheta_i = j (c - a),
 // dS_i/d|V_i| = (a + c) / |V_i|.  Theta rows take the real part, Q rows the
 // imaginary part (kind = 2 row type + column type).
-template <int BLOCK, int KB>
+// Byte offset of the staged schedule tables in the direct kernel's LDS.
+__host__ __device__ inline size_t direct_stage_offset(int nbp, int nw, const DirectDev& d) {
+  return ((size_t)2 * nbp * 16 + (size_t)2 * nw * 8 + ((size_t)d.n_val + 2 * d.m) * 8 + 15) / 16 * 16;
+}
+__host__ __device__ inline size_t direct_stage_bytes(const DirectDev& d) {
+  return (size_t)16 * (d.n_tg + d.n_ct + d.n_je) +
+         (size_t)4 * ((d.m + 1) + d.n_s + d.m + (d.n_fph + 1) + (d.n_bph + 1));
+}
+
+// STAGE: the schedule tables (targets, contributions, J entries, S(k) and the
+// level lists) are copied into LDS once per workgroup, so each phase reads
+// them at LDS latency instead of an L2 round trip (when they fit).
+template <int BLOCK, int KB, bool STAGE>
 __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* __restrict__ netp, DirectDev d,
                                                           NRLaunch a) {
   constexpr int NW = BLOCK / WAVE;
@@ -1014,6 +1026,35 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
   double* val = red + 2 * NW;
   double* rhs = val + d.n_val;
   double* xs = rhs + m;
+  int4 *ltg = nullptr, *lct = nullptr, *lje = nullptr;
+  int *lso = nullptr, *lsi = nullptr, *lbr = nullptr, *lfp = nullptr, *lbp = nullptr;
+  if constexpr (STAGE) {
+    ltg = reinterpret_cast<int4*>(smem + direct_stage_offset(NBP, NW, d));
+    lct = ltg + d.n_tg;
+    lje = lct + d.n_ct;
+    lso = reinterpret_cast<int*>(lje + d.n_je);
+    lsi = lso + m + 1;
+    lbr = lsi + ns;
+    lfp = lbr + m;
+    lbp = lfp + d.n_fph + 1;
+    for (int q = tid; q < d.n_tg; q += BLOCK) ltg[q] = cld(d.ftg, (unsigned)q);
+    for (int q = tid; q < d.n_ct; q += BLOCK) lct[q] = cld(d.fct, (unsigned)q);
+    for (int q = tid; q < d.n_je; q += BLOCK) lje[q] = cld(d.je, (unsigned)q);
+    for (int q = tid; q <= m; q += BLOCK) lso[q] = cld(d.soff, (unsigned)q);
+    for (int q = tid; q < ns; q += BLOCK) lsi[q] = cld(d.sidx, (unsigned)q);
+    for (int q = tid; q < m; q += BLOCK) lbr[q] = cld(d.brow, (unsigned)q);
+    for (int q = tid; q <= d.n_fph; q += BLOCK) lfp[q] = cld(d.fph, (unsigned)q);
+    for (int q = tid; q <= d.n_bph; q += BLOCK) lbp[q] = cld(d.bph, (unsigned)q);
+    // (made visible by the barriers of the first mismatch)
+  }
+  auto TG = [&](int q) { if constexpr (STAGE) return ltg[q]; else return cld(d.ftg, (unsigned)q); };
+  auto CT = [&](int q) { if constexpr (STAGE) return lct[q]; else return cld(d.fct, (unsigned)q); };
+  auto JE = [&](int q) { if constexpr (STAGE) return lje[q]; else return cld(d.je, (unsigned)q); };
+  auto SO = [&](int q) { if constexpr (STAGE) return lso[q]; else return cld(d.soff, (unsigned)q); };
+  auto SI = [&](int q) { if constexpr (STAGE) return lsi[q]; else return cld(d.sidx, (unsigned)q); };
+  auto BR = [&](int q) { if constexpr (STAGE) return lbr[q]; else return cld(d.brow, (unsigned)q); };
+  auto FPH = [&](int q) { if constexpr (STAGE) return lfp[q]; else return cld(d.fph, (unsigned)q); };
+  auto BPH = [&](int q) { if constexpr (STAGE) return lbp[q]; else return cld(d.bph, (unsigned)q); };
 
   const Ws<BLOCK, KB> ws{make_buf(a.ws_d + (int64_t)b * a.ws_d_stride)};
   const Buf P = make_buf(a.p_inj + (int64_t)b * a.ld);
@@ -1067,7 +1108,7 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
       const TxDev<double> net = load_desc(netp);
       const double2* yvals = yv ? yv : net.y64.val;
       for (int e = tid; e < d.n_je; e += BLOCK) {
-        const int4 E = cld(d.je, (unsigned)e);
+        const int4 E = JE(e);
         const int pos = E.x & 0x0fffffff, kind = (int)((unsigned)E.x >> 28);
         const double2 vi = vs[E.y], vk = vs[E.z], y = cld(yvals, (unsigned)E.w);
         const double tr = y.x * vk.x - y.y * vk.y, ti = y.x * vk.y + y.y * vk.x;  // Y_ik V_k
@@ -1099,12 +1140,12 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
     // read only their own row, column and rhs entry, which no pivot of the
     // level changes, and L stays unscaled (its entries hold L U[k][k]).
     for (int ph = 0; ph < d.n_fph; ++ph) {
-      const int q1 = cld(d.fph, (unsigned)(ph + 1));
-      for (int q = cld(d.fph, (unsigned)ph) + tid; q < q1; q += BLOCK) {
-        const int4 T = cld(d.ftg, (unsigned)q);
+      const int q1 = FPH(ph + 1);
+      for (int q = FPH(ph) + tid; q < q1; q += BLOCK) {
+        const int4 T = TG(q);
         double acc = 0.0;
         for (int c = T.y; c < T.z; ++c) {
-          const int4 C = cld(d.fct, (unsigned)c);
+          const int4 C = CT(c);
           acc += val[C.x] * (T.w ? rhs[C.y] : val[C.y]) / val[C.z];
         }
         if (T.w) rhs[T.x] -= acc;
@@ -1115,12 +1156,12 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
     // backward: U x = y by levels, one thread per row: x_k = (y_k - U[k][S(k)]
     // x[S(k)]) / U[k][k], the x it reads solved in earlier levels
     for (int ph = 0; ph < d.n_bph; ++ph) {
-      const int q1 = cld(d.bph, (unsigned)(ph + 1));
-      for (int q = cld(d.bph, (unsigned)ph) + tid; q < q1; q += BLOCK) {
-        const int k = cld(d.brow, (unsigned)q);
-        const int s1 = cld(d.soff, (unsigned)(k + 1));
+      const int q1 = BPH(ph + 1);
+      for (int q = BPH(ph) + tid; q < q1; q += BLOCK) {
+        const int k = BR(q);
+        const int s1 = SO(k + 1);
         double acc = rhs[k];
-        for (int t = cld(d.soff, (unsigned)k); t < s1; ++t) acc -= val[m + ns + t] * xs[cld(d.sidx, (unsigned)t)];
+        for (int t = SO(k); t < s1; ++t) acc -= val[m + ns + t] * xs[SI(t)];
         xs[k] = acc / val[k];
       }
       __syncthreads();
@@ -1430,10 +1471,14 @@ struct NrDirectGo {
   template <int BLOCK, int KB>
   void operator()() const {
     const DirectDev& d = net.direct;
-    const size_t lds = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
-    if (lds > 160 * 1024)
-      fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(lds) + " bytes of LDS)");
-    auto kernel = nr_direct_kernel<BLOCK, KB>;
+    const size_t lds0 = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
+    if (lds0 > 160 * 1024)
+      fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(lds0) + " bytes of LDS)");
+    // stage the schedule tables when the total stays within 64 KB
+    const size_t lds1 = direct_stage_offset(KB * BLOCK, BLOCK / WAVE, d) + direct_stage_bytes(d);
+    const bool stage = lds1 <= 64 * 1024;
+    const size_t lds = stage ? lds1 : lds0;
+    auto kernel = stage ? nr_direct_kernel<BLOCK, KB, true> : nr_direct_kernel<BLOCK, KB, false>;
     if (lds > 64 * 1024)
       PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));

@@ -69,7 +69,7 @@ struct TxDev {
 
 // Device view of the direct Newton step's shared analysis (direct.hpp).
 struct DirectDev {
-  int m, n_s, n_val, n_je, n_fph, n_bph;
+  int m, n_s, n_val, n_je, n_fph, n_bph, n_tg, n_ct;
   const int* fpos;   // [2 nbp]
   const int* soff;   // [m + 1]
   const int* sidx;

@@ -431,6 +431,8 @@ void ensure_direct(TxNetwork& net) {
   d.n_je = (int)D.je.size() / 4;
   d.n_fph = (int)D.fph.size() - 1;
   d.n_bph = (int)D.bph.size() - 1;
+  d.n_tg = (int)D.ftg.size() / 4;
+  d.n_ct = (int)D.fct.size() / 4;
   d.fpos = net.dl_fpos.as<int>();
   d.soff = net.dl_soff.as<int>();
   d.sidx = net.dl_sidx.as<int>();
