@@ -140,14 +140,9 @@ class TxNetwork:
             L.lib().pf_tx_network_destroy(self.h)
             self.h = c_void_p()
 
-    def solve(self, p_inj: torch.Tensor, q_inj: torch.Tensor, vm_set: torch.Tensor, *, stream=None,
-              out: TxResult | None = None, **opts) -> TxResult:
-        """Batched Newton-Raphson from a flat start; see pf_tx_solve."""
+    def _out(self, out: "TxResult | None", B: int, ld: int, dev) -> "TxResult":
+        """The caller's output tensors (rows at the input stride) or new ones."""
         n = self.n_bus
-        ld = _ld((p_inj, n, torch.float64, "p_inj"), (q_inj, n, torch.float64, "q_inj"),
-                 (vm_set, n, torch.float64, "vm_set"))
-        B = int(p_inj.shape[0])
-        dev = p_inj.device
         if out is None:
             out = TxResult(v=torch.empty((B, n), dtype=torch.complex128, device=dev),
                            newton_iters=torch.empty(B, dtype=torch.int32, device=dev),
@@ -157,6 +152,17 @@ class TxNetwork:
                            work_bytes=torch.empty(B, dtype=torch.float64, device=dev))
         if B > 1 and out.v.stride(0) != ld:
             raise ValueError("output rows must use the input row stride")
+        return out
+
+    def solve(self, p_inj: torch.Tensor, q_inj: torch.Tensor, vm_set: torch.Tensor, *, stream=None,
+              out: TxResult | None = None, **opts) -> TxResult:
+        """Batched Newton-Raphson from a flat start; see pf_tx_solve."""
+        n = self.n_bus
+        ld = _ld((p_inj, n, torch.float64, "p_inj"), (q_inj, n, torch.float64, "q_inj"),
+                 (vm_set, n, torch.float64, "vm_set"))
+        B = int(p_inj.shape[0])
+        dev = p_inj.device
+        out = self._out(out, B, ld, dev)
         o = L.opts(**opts)
         L.call("pf_tx_solve", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
                _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters), _dptr(out.converged),
@@ -192,15 +198,7 @@ class TxNetwork:
         if int(y_vals.shape[0]) != B:
             raise ValueError("y_vals must have one row per scenario")
         dev = p_inj.device
-        if out is None:
-            out = TxResult(v=torch.empty((B, n), dtype=torch.complex128, device=dev),
-                           newton_iters=torch.empty(B, dtype=torch.int32, device=dev),
-                           gmres_iters=torch.empty(B, dtype=torch.int32, device=dev),
-                           converged=torch.empty(B, dtype=torch.uint8, device=dev),
-                           mismatch=torch.empty(B, dtype=torch.float64, device=dev),
-                           work_bytes=torch.empty(B, dtype=torch.float64, device=dev))
-        if B > 1 and out.v.stride(0) != ld:
-            raise ValueError("output rows must use the input row stride")
+        out = self._out(out, B, ld, dev)
         o = L.opts(**opts)
         L.call("pf_tx_solve_yvals", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
                ldy, _dptr(y_vals), _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters),
