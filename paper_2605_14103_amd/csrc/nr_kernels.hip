@@ -1474,9 +1474,11 @@ struct NrDirectGo {
     const size_t lds0 = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
     if (lds0 > 160 * 1024)
       fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(lds0) + " bytes of LDS)");
-    // stage the schedule tables when the total stays within 64 KB
+    // stage the schedule tables when the total stays within 64 KB, or, when
+    // the batch has no more scenarios than the chip has CUs (one workgroup
+    // per CU, occupancy moot), within the CU's 160 KB
     const size_t lds1 = direct_stage_offset(KB * BLOCK, BLOCK / WAVE, d) + direct_stage_bytes(d);
-    const bool stage = lds1 <= 64 * 1024;
+    const bool stage = lds1 <= (a.batch <= 256 ? 160 : 64) * 1024;
     const size_t lds = stage ? lds1 : lds0;
     auto kernel = stage ? nr_direct_kernel<BLOCK, KB, true> : nr_direct_kernel<BLOCK, KB, false>;
     if (lds > 64 * 1024)
