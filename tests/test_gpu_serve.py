@@ -123,6 +123,9 @@ def test_admission_limits_and_lifetime(ctx):
     with pytest.raises(L.PfError) as e:
         pf.Engine(net, hbm_bytes=slot - 1)
     assert e.value.status == L.PF_INVALID_ARG
+    with pytest.raises(L.PfError) as e:  # the engine runs the GMRES step only
+        pf.Engine(net, hbm_bytes=4 * slot, nr_direct=1)
+    assert e.value.status == L.PF_INVALID_ARG and "nr_direct" in str(e.value)
     eng = pf.Engine(net, hbm_bytes=4 * slot, n_streams=1)
     assert eng.info()["max_slots"] == 4
     b = tx.make_batch(grid, tx.TX30, batch=5, seed=1)
