@@ -159,6 +159,11 @@ pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* 
  * 32n + 16m, per Newton update 16m, with w = 8 (PF_FP64) or 4 (PF_MIXED) and
  * m = |Theta| + |Q|).  Optional outputs
  * may be null: gmres_iters, final_mismatch, work_bytes.  batch may be 0.
+ * With opts->nr_direct = 1 each Newton step is solved exactly by a sparse LU
+ * of J (FP64 whatever opts->precision says; gmres_iters reports 0; the
+ * byte model counts the mismatch plus 40m per step); the network's shared
+ * analysis is built on the first such call, and a network whose factor
+ * exceeds the per-scenario limit is refused with PF_INVALID_ARG.
  * Errors: PF_INVALID_ARG (ld < n_bus, batch < 0, bad options),
  * PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_tx_solve(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
