@@ -136,20 +136,23 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     if (batch == 0) return;
     require(s_wye && s_delta && v_out && iters && converged, "null required pointer");
     activate(net->ctx);
+    const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(net->order.mu);
     const bool mixed = o.precision == PF_MIXED;
     const int rows = (batch + ZB_BM - 1) / ZB_BM * ZB_BM;
     const size_t tsz = mixed ? sizeof(float) : sizeof(double);
-    net->ws_v.ensure(net->ctx, (size_t)batch * net->Kp * sizeof(double));
+    net->order.grow(net->ws_v, net->ctx, (size_t)batch * net->Kp * sizeof(double));
     const size_t rbytes = (size_t)rows * net->Kp * tsz;
     if (net->ws_r.bytes() < rbytes) {
-      net->ws_r.ensure(net->ctx, rbytes);
+      net->order.grow(net->ws_r, net->ctx, rbytes);
       // padding rows and columns of R must read as zeros
       PFX_HIP(hipMemset(net->ws_r.as<void>(), 0, net->ws_r.bytes()));
     }
-    net->ws_s.ensure(net->ctx, (size_t)batch * 3 * sizeof(double));
-    net->ws_act.ensure(net->ctx, (size_t)rows * sizeof(int32_t));
-    net->ws_cnt.ensure(net->ctx, (size_t)(o.zbus_max_iter + 1) * sizeof(int32_t));
+    net->order.grow(net->ws_s, net->ctx, (size_t)batch * 3 * sizeof(double));
+    net->order.grow(net->ws_act, net->ctx, (size_t)rows * sizeof(int32_t));
+    net->order.grow(net->ws_cnt, net->ctx, (size_t)(o.zbus_max_iter + 1) * sizeof(int32_t));
     if (net->count_host_len < o.zbus_max_iter + 1) {
+      net->order.drain();
       if (net->count_host) PFX_HIP(hipHostFree(net->count_host));
       net->count_host = nullptr;
       PFX_HIP(hipHostMalloc(reinterpret_cast<void**>(&net->count_host),
@@ -175,7 +178,9 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     a.active = net->ws_act.as<int32_t>();
     a.count = net->ws_cnt.as<int32_t>();
     a.count_host = net->count_host;
-    run_zbus(*net, mixed, a, reinterpret_cast<hipStream_t>(stream));
+    net->order.begin(hs);
+    run_zbus(*net, mixed, a, hs);
+    net->order.end(hs);
   });
 }
 

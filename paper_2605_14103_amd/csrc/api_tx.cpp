@@ -117,18 +117,24 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   require(p_inj && q_inj && vm_set && v_out && newton_iters && converged, "null required pointer");
   activate(net->ctx);
   const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(net->order.mu);
   const bool direct = o.nr_direct == 1;
-  if (direct) ensure_direct(*net);
+  if (direct) {
+    net->order.drain();   // the analysis is written into the network once, with no call in flight
+    ensure_direct(*net);
+  }
   const bool mixed = o.precision == PF_MIXED && !direct;
   const int64_t dstride = nr_ws_doubles(*net);
   const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
-  net->ws_d.ensure(net->ctx, (size_t)batch * dstride * sizeof(double));
-  if (!direct) net->ws_basis.ensure(net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
+  net->order.grow(net->ws_d, net->ctx, (size_t)batch * dstride * sizeof(double));
+  if (!direct)
+    net->order.grow(net->ws_basis, net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
+  net->order.begin(hs);
   NRLaunch a{};
   if (y_vals) {
     // FP64 layout copy, then (mixed) the FP32 copy behind it
     const size_t n64 = (size_t)batch * net->y_entries;
-    net->ws_y.ensure(net->ctx, n64 * sizeof(double2) + (mixed ? n64 * sizeof(float2) : 0));
+    net->order.grow(net->ws_y, net->ctx, n64 * sizeof(double2) + (mixed ? n64 * sizeof(float2) : 0));
     double2* y64 = net->ws_y.as<double2>();
     float2* y32 = mixed ? reinterpret_cast<float2*>(y64 + n64) : nullptr;
     launch_y_gather(*net, batch, ldy, y_vals, y64, y32, hs);
@@ -160,6 +166,7 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   a.ws_b_stride = bstride;
   if (direct) launch_nr_direct(*net, a, hs);
   else launch_nr(*net, mixed, a, hs);
+  net->order.end(hs);
 }
 
 }  // namespace
@@ -271,7 +278,10 @@ pf_status pf_tx_adjoint(pf_tx_network* h, const pf_opts* opts, int32_t batch, in
     const double rtol = (opts && opts->gmres_rtol > 0) ? opts->gmres_rtol : 1e-10;
     const int64_t dstride = adj_ws_doubles(*net);
     const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
-    net->ws_adj.ensure(net->ctx, (size_t)batch * (dstride + bstride) * sizeof(double));
+    const hipStream_t hs = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(net->order.mu);
+    net->order.grow(net->ws_adj, net->ctx, (size_t)batch * (dstride + bstride) * sizeof(double));
+    net->order.begin(hs);
     AdjLaunch a{};
     a.batch = batch;
     a.ld = ld;
@@ -288,7 +298,8 @@ pf_status pf_tx_adjoint(pf_tx_network* h, const pf_opts* opts, int32_t batch, in
     a.ws_d_stride = dstride;
     a.ws_basis = net->ws_adj.as<double>() + (int64_t)batch * dstride;
     a.ws_b_stride = bstride;
-    launch_adjoint(*net, a, reinterpret_cast<hipStream_t>(stream));
+    launch_adjoint(*net, a, hs);
+    net->order.end(hs);
   });
 }
 

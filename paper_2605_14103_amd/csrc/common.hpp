@@ -91,6 +91,41 @@ DeviceBuffer upload(Context* ctx, const std::vector<T>& v) {
   return b;
 }
 
+// Orders the calls that share one network's workspace.  A call holds `mu` on
+// the host for as long as it enqueues work; on the device its stream first
+// waits for the previous call's work, which may sit on another stream, and
+// then records its own completion, so two calls enqueued on different streams
+// never run over the same workspace at once.  A workspace is reallocated only
+// after the host has waited for the previous call's work.
+struct CallOrder {
+  std::mutex mu;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+  CallOrder() = default;
+  CallOrder(const CallOrder&) = delete;
+  CallOrder& operator=(const CallOrder&) = delete;
+  ~CallOrder() {
+    if (ev) (void)hipEventDestroy(ev);
+  }
+  void begin(hipStream_t s) {
+    if (!ev) PFX_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (pending) PFX_HIP(hipStreamWaitEvent(s, ev, 0));
+  }
+  void end(hipStream_t s) {
+    PFX_HIP(hipEventRecord(ev, s));
+    pending = true;
+  }
+  void drain() {
+    if (pending) PFX_HIP(hipEventSynchronize(ev));
+  }
+  void grow(DeviceBuffer& b, Context* ctx, size_t bytes) {
+    if (bytes > b.bytes()) {
+      drain();
+      b.ensure(ctx, bytes);
+    }
+  }
+};
+
 struct Context {
   int device = 0;
   uint64_t budget = 0;       // 0 = unbounded

@@ -71,6 +71,7 @@ struct DistNetwork {
   DeviceBuffer vslack_d;   // 6 doubles
   // workspaces (grow-only); calls on one network must not overlap
   DeviceBuffer ws_v, ws_r, ws_s, ws_act, ws_cnt;
+  CallOrder order;   // orders the solves that share these workspaces
   int32_t* count_host = nullptr;   // pinned readback of the active counts
   int count_host_len = 0;
   ~DistNetwork();

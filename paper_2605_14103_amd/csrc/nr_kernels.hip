@@ -1483,7 +1483,7 @@ struct NrDirectGo {
     // the batch has no more scenarios than the chip has CUs (one workgroup
     // per CU, occupancy moot), within the CU's 160 KB
     const size_t lds1 = direct_stage_offset(KB * BLOCK, BLOCK / WAVE, d) + direct_stage_bytes(d);
-    const bool stage = lds1 <= (a.batch <= 256 ? 160 : 64) * 1024;
+    const bool stage = lds1 <= (a.batch <= net.ctx->cu_count ? 160 : 64) * 1024;
     const size_t lds = stage ? lds1 : lds0;
     auto kernel = stage ? nr_direct_kernel<BLOCK, KB, true> : nr_direct_kernel<BLOCK, KB, false>;
     if (lds > 64 * 1024)

@@ -116,8 +116,9 @@ struct TxNetwork {
   int direct_nval = 0;
   DirectDev direct{};
   DeviceBuffer dl_fpos, dl_soff, dl_sidx, dl_fph, dl_ftg, dl_fct, dl_bph, dl_brow, dl_je;
-  // solve workspaces (grow-only); calls on one network must not overlap
+  // solve workspaces (grow-only), shared by the network's calls and ordered by `order`
   DeviceBuffer ws_d, ws_basis, ws_adj, ws_y;
+  CallOrder order;
   // the device views themselves, resident in device memory so kernels take one pointer
   DeviceBuffer desc64, desc32;
   template <typename T>

@@ -184,3 +184,69 @@ def test_short_trace_replay(ctx):
         e.close()
     for n in nets:
         n.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_networks_in_one_mix(ctx, precision):
+    """The serving mix's own networks at full size: the 2000-bus grid and the
+    900-node feeder, with the 30-bus grid, each behind its engine; requests of
+    1 to 512 scenarios are submitted interleaved so that the three engines run
+    at once.  Every request equals its solve alone bit for bit, and scenarios
+    spread over the requests match the oracle."""
+    from paper_2605_14103_amd import pf
+    prec = pf.precision(precision)
+    g30 = tx.make_grid(tx.TX30)
+    g2k = tx.make_grid(tx.TX2000)
+    fd = fdm.make_feeder(fdm.FEEDER300)
+    nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k), pf.DistNetwork.from_feeder(ctx, fd)]
+    engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=prec)
+               for n, b, s in zip(nets, (256 << 20, 4 << 30, 1 << 30), (1, 2, 1))]
+    sizes = {0: [5, 64, 1], 1: [1, 37, 512, 3, 200], 2: [3, 300, 1, 129, 512]}
+    reqs = []
+    for k in range(max(len(v) for v in sizes.values())):
+        for net_id, sz in sizes.items():
+            if k < len(sz):
+                seed = 900 + 10 * net_id + k
+                if net_id == 0:
+                    b = tx.make_batch(g30, tx.TX30, batch=sz[k], seed=seed)
+                    arrays = (b.p_inj, b.q_inj, b.vm_set)
+                elif net_id == 1:
+                    b = tx.make_batch(g2k, tx.TX2000, batch=sz[k], seed=seed)
+                    arrays = (b.p_inj, b.q_inj, b.vm_set)
+                else:
+                    b = fdm.make_batch(fd, fdm.FEEDER300, batch=sz[k], seed=seed)
+                    arrays = (b.s_wye, b.s_delta)
+                rid = len(reqs)
+                reqs.append((net_id, rid, b, arrays))
+                engines[net_id].submit(rid, *arrays)
+    got = {}
+    for net_id in range(3):
+        ids = [rid for n, rid, _, _ in reqs if n == net_id]
+        got.update(_collect(engines[net_id], ids, timeout=90.0))
+    say(f"full-size mix {precision}:", [e.info() for e in engines])
+    for net_id, rid, b, arrays in reqs:
+        r = got[rid]
+        if net_id == 2:
+            v, it, ok = _alone_dist(nets[2], *arrays, precision=prec)
+        else:
+            v, it, ok = _alone_tx(nets[net_id], *arrays, precision=prec)
+        assert r.converged.all() and ok.all(), f"request {rid} (network {net_id}) did not converge"
+        assert r.mismatch.max() <= 1e-8
+        assert np.array_equal(r.v.view(np.float64), v.view(np.float64)), f"request {rid} differs from alone"
+        assert np.array_equal(r.iters, it)
+    # oracle: two scenarios of every 2000-bus and feeder request (first and last)
+    for net_id, rid, b, arrays in reqs:
+        cols = np.unique([0, b.batch - 1] if net_id else [0])
+        if net_id == 1:
+            V, _, ok, _ = onr.nr_solve_batch(g2k, b, columns=cols)
+        elif net_id == 2:
+            ref = ozb.zbus_solve(fd, fdm.FeederBatch(b.s_wye[cols], b.s_delta[cols]))
+            V, ok = ref.v, ref.converged
+        else:
+            V, _, ok, _ = onr.nr_solve_batch(g30, b, columns=cols)
+        da, dm = angle_err(got[rid].v[cols], V)
+        assert ok.all() and da <= 1e-6 and dm <= 1e-6, f"request {rid}: {da:.2e} rad, {dm:.2e} pu"
+    for e in engines:
+        e.close()
+    for n in nets:
+        n.close()

@@ -5,7 +5,7 @@ import pytest
 
 from oracle import adjoint as oadj
 from oracle import nr as onr
-from tests.gpu_common import angle_err, say, to_dev
+from tests.gpu_common import HV_FLOOR_TX, angle_err, assert_high_voltage, say, spread_cols, to_dev
 from workloads import transmission as tx
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +57,7 @@ def test_tx30_full_batch(ctx, precision):
     batch = tx.make_batch(grid, tx.TX30)
     net = pf.TxNetwork.from_grid(ctx, grid)
     res = _solve(net, batch, precision=pf.precision(precision))
+    assert_high_voltage(res.v.cpu().numpy(), HV_FLOOR_TX, f"tx30 {precision}")
     _check_against_oracle(grid, batch, res, np.arange(batch.batch), precision)
     net.close()
 
@@ -73,8 +74,8 @@ def test_tx2000_full_batch_sampled(ctx, precision):
     res = _solve(net, batch, precision=pf.precision(precision))
     assert res.converged.cpu().numpy().all()
     assert res.mismatch.cpu().numpy().max() <= 1e-8
-    cols = np.array([0, 1, 511, 1023])
-    _check_against_oracle(grid, batch, res, cols, precision)
+    assert_high_voltage(res.v.cpu().numpy(), HV_FLOOR_TX, f"tx2000 {precision}")
+    _check_against_oracle(grid, batch, res, spread_cols(batch.batch, 32), precision)
     net.close()
 
 
@@ -345,7 +346,7 @@ def test_branch_outages_against_oracle(ctx, precision):
     admittance matrix."""
     import torch
     from paper_2605_14103_amd import pf
-    for cfg, n_out, cols in ((tx.TX30, 2, None), (tx.TX2000, 1, np.array([0, 1, 700, 1023]))):
+    for cfg, n_out, cols in ((tx.TX30, 2, None), (tx.TX2000, 1, spread_cols(tx.TX2000.batch, 32))):
         grid = tx.make_grid(cfg)
         batch = tx.make_batch(grid, cfg)
         on = tx.make_outages(grid, batch.batch, n_out=n_out, seed=cfg.seed + 7)
@@ -354,6 +355,9 @@ def test_branch_outages_against_oracle(ctx, precision):
         res = _solve_yvals(net, batch, yv, precision=pf.precision(precision))
         conv = res.converged.cpu().numpy()
         say(f"{cfg.name} outages {precision}: converged {int(conv.sum())} of {batch.batch}")
+        # the converged scenarios reached the high-voltage solution; the
+        # outages that leave none near flat start report converged = 0
+        assert_high_voltage(res.v.cpu().numpy()[conv.astype(bool)], HV_FLOOR_TX, f"{cfg.name} outages")
         _check_outages(grid, batch, on, res, np.arange(batch.batch) if cols is None else cols,
                        f"{cfg.name} {n_out} out {precision}")
         net.close()
@@ -479,4 +483,90 @@ def test_direct_edge_cases_and_isolation(ctx):
     # the direct step ignores the precision option (always FP64): same result
     mixed = _solve(net, batch, nr_direct=1, precision=pf.precision("mixed"))
     assert torch.equal(mixed.v, ref.v)
+    net.close()
+
+
+def test_adjoint_tx2000_against_central_differences(ctx):
+    """The sensitivity workload at full shape: the 2000-bus grid, batch 256,
+    GPU gradients of the branch loss with respect to 64 seeded injections (32 P
+    on Theta buses, 32 Q on PQ buses) in 4 scenarios, against central
+    differences (h = 1e-6) of the oracle's solves.  Each perturbed solve takes
+    two exact Newton steps from the unperturbed solution, which drives it to
+    rounding level (quadratic convergence from 1e-6 away), as the check needs."""
+    from paper_2605_14103_amd import pf
+    cfg = tx.TX2000_ADJ
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    res = _solve(net, batch, tol=1e-11)
+    assert res.converged.cpu().numpy().all()
+    loss, g = net.branch_loss(res.v)
+    gp, gq, its, ok = net.adjoint(res.v, g)
+    assert ok.cpu().numpy().all()
+    gp = gp.cpu().numpy()
+    gq = gq.cpu().numpy()
+    Y = onr.ybus(grid.n_bus, grid.f, grid.t, grid.r, grid.x, grid.b)
+    theta = np.flatnonzero(grid.bus_type != tx.SLACK)
+    pq = np.flatnonzero(grid.bus_type == tx.PQ)
+    rng = np.random.default_rng(2024)
+    p_idx = rng.choice(theta, 32, replace=False)
+    q_idx = rng.choice(pq, 32, replace=False)
+    h = 1e-6
+    for c in (0, 85, 170, 255):
+        p0, q0, vs = batch.p_inj[c], batch.q_inj[c], batch.vm_set[c]
+        base = onr.nr_solve(Y, grid.bus_type, p0, q0, vs, tol=1e-12)
+        assert base.mismatch <= 1e-10
+
+        def L(pp, qq):
+            r = onr.nr_solve(Y, grid.bus_type, pp, qq, vs, tol=0.0, max_iter=2, V0=base.V)
+            assert r.mismatch <= 1e-10
+            return float(oadj.branch_loss(grid, r.V))
+
+        scale = max(np.abs(gp[c]).max(), np.abs(gq[c]).max())
+        worst = 0.0
+        for k in p_idx:
+            e = np.zeros(grid.n_bus)
+            e[k] = h
+            fd = (L(p0 + e, q0) - L(p0 - e, q0)) / (2 * h)
+            worst = max(worst, abs(fd - gp[c, k]) / scale)
+        for k in q_idx:
+            e = np.zeros(grid.n_bus)
+            e[k] = h
+            fd = (L(p0, q0 + e) - L(p0, q0 - e)) / (2 * h)
+            worst = max(worst, abs(fd - gq[c, k]) / scale)
+        say(f"tx2000 adjoint vs central differences, scenario {c}: max err {worst:.2e} of max |grad| "
+            f"{scale:.3e}, adjoint gmres {int(its[c])}")
+        assert worst <= 1e-5
+    net.close()
+
+
+def test_autograd_reports_nonconvergence(ctx):
+    """A backward pass through a scenario whose forward solve or adjoint solve
+    did not converge raises (the default) or, with on_failure="zero", warns and
+    returns zero gradient rows for it; a converged batch passes."""
+    from paper_2605_14103_amd import autograd, pf
+    grid = tx.make_grid(tx.TX30)
+    batch = tx.make_batch(grid, tx.TX30, batch=3)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+
+    def run(**kw):
+        p = to_dev(batch.p_inj).requires_grad_(True)
+        q = to_dev(batch.q_inj).requires_grad_(True)
+        v, conv = autograd.solve(net, p, q, to_dev(batch.vm_set), **kw)
+        (v.abs() ** 2).sum().backward()
+        return p.grad.cpu().numpy(), q.grad.cpu().numpy()
+
+    # adjoint starved: one Arnoldi step in one cycle cannot reach its 1e-10 tolerance
+    with pytest.raises(autograd.NonConvergedGradient) as e:
+        run(adjoint_opts={"gmres_restart": 1, "gmres_max_restarts": 1})
+    assert e.value.adjoint_failed and not e.value.forward_failed
+    # forward capped at one Newton update: no scenario converges
+    with pytest.raises(autograd.NonConvergedGradient) as e:
+        run(max_newton=1)
+    assert e.value.forward_failed == [0, 1, 2]
+    with pytest.warns(RuntimeWarning):
+        gp, gq = run(max_newton=1, on_failure="zero")
+    assert (gp == 0).all() and (gq == 0).all()
+    gp, gq = run()
+    assert np.abs(gp).max() > 0 and np.isfinite(gp).all() and np.isfinite(gq).all()
     net.close()
