@@ -82,6 +82,9 @@ typedef struct pf_opts {
                                  per-scenario sparse LU of J on a shared symbolic analysis (the
                                  sparse direct outlook of Sec. IV), always in FP64, for networks
                                  whose factor fits the per-scenario limit (12288 values) */
+  /* serving engine */
+  int32_t step_iters;         /* Newton updates or fixed-point iterations per engine step of a
+                                 request-driven engine, 1..1000, default 1 */
 } pf_opts;
 
 void pf_opts_default(pf_opts* out);
@@ -279,37 +282,81 @@ pf_status pf_dist_solve(pf_dist_network* net, const pf_opts* opts, int32_t batch
 
 /* ------------------------------------------------------------- serving */
 
-/* Serving engine: continuous batching of solve requests for one registered
- * network (the batched solves of Sec. II-A or II-B, served as the requests of
- * the paper's many-scenario setting arrive).  The engine owns device memory
- * for max_slots = floor(hbm_bytes / slot_bytes) scenario slots (inputs,
- * outputs and solver workspace) and n_streams HIP streams, each run by a
- * worker thread.  Requests wait in FIFO order; whenever a stream is idle the
- * longest FIFO prefix of waiting requests that fits one contiguous run of
- * free slots is launched on it as one batched solve, so requests arriving
- * while others run are admitted as soon as slots and a stream free up and
- * their kernels overlap with the running ones.  Every scenario's arithmetic is
- * independent of the other scenarios in its launch, so results are
- * bit-identical to a solve of the request alone.  Options (precision,
- * tolerances) are fixed at creation.  An engine is bound to its network and
- * context: destroying either destroys the engine (pending requests are
- * dropped).  The engine's calls are thread-safe. */
+/* Serving engine: step-level continuous batching of scenarios for one
+ * registered network (the batched solves of Sec. II-A or II-B, served as the
+ * requests of the paper's many-scenario setting arrive).  The engine owns
+ * device memory for max_slots scenario slots (inputs, outputs, the
+ * resumable solver state and workspace; max_slots = floor(hbm_bytes /
+ * slot_bytes), a little less for a feeder engine with several streams).  A
+ * step advances every occupied slot by at most a given number of Newton
+ * updates (transmission) or Z-bus fixed-point iterations (feeder) in one
+ * launch over the occupied slots; between steps finished scenarios are
+ * harvested and waiting ones admitted into any free slots.  A scenario
+ * resumes each step exactly where the previous one stopped, so its result is
+ * bit-identical to pf_tx_solve / pf_dist_solve of that scenario with the
+ * engine's options, whatever shares its steps.  Options (precision,
+ * tolerances, step_iters) are fixed at creation; the direct Newton step is
+ * not available (nr_direct must be 0).  An engine is bound to its network
+ * and context: destroying either destroys the engine (waiting requests are
+ * dropped).  The engine's calls are thread-safe.
+ *
+ * Two ways to drive an engine:
+ *   caller-driven (n_streams = 0): pf_engine_admit, pf_engine_step and
+ *     pf_engine_harvest on streams the caller names;
+ *   request-driven (n_streams = 1..8): pf_engine_submit queues requests of
+ *     any size; each of n_streams cohorts (a HIP stream run by a host thread
+ *     of the engine) repeats admit -> step (opts->step_iters iterations) ->
+ *     harvest.  Requests are admitted in arrival order into any free slots
+ *     (not necessarily contiguous), all of a request's scenarios into one
+ *     cohort; a request too large for the free slots may be passed by later
+ *     requests at most 8 times.  pf_engine_poll and pf_engine_fetch report a
+ *     request once its last scenario is harvested.  The cohorts' kernels
+ *     overlap on the device, and so do those of engines on other networks. */
 
 /* Device bytes of one slot for `opts` (exactly one of tx, dist non-null). */
 pf_status pf_engine_slot_bytes(pf_tx_network* tx, pf_dist_network* dist, const pf_opts* opts,
                                uint64_t* bytes);
 /* Create an engine over exactly one of tx or dist.  hbm_bytes bounds the slot
- * memory (PF_INVALID_ARG if below one slot); n_streams in 1..8; opts may be
- * null.  Errors: PF_INVALID_ARG, PF_BAD_HANDLE, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
+ * memory (PF_INVALID_ARG if below one slot); n_streams in 0..8 (0:
+ * caller-driven); opts may be null.
+ * Errors: PF_INVALID_ARG, PF_BAD_HANDLE, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_engine_create(pf_context* ctx, pf_tx_network* tx, pf_dist_network* dist, uint64_t hbm_bytes,
                            int32_t n_streams, const pf_opts* opts, pf_engine** out);
 void pf_engine_destroy(pf_engine* engine);
-/* Queue request `id` (caller-chosen, unique among unfetched requests) of n
- * scenarios.  Host inputs, copied before return, [n][row]: transmission:
- * in0 = p_inj, in1 = q_inj, in2 = vm_set (row = n_bus, as in pf_tx_solve);
- * feeder: in0 = s_wye, in1 = s_delta complex (row = 2 n_node doubles, as in
- * pf_dist_solve), in2 unused.  Errors: PF_NOT_ADMITTED (n exceeds the
- * engine's slots), PF_INVALID_ARG (n < 1, duplicate id, null input). */
+
+/* Caller-driven engines.  Place n scenarios into the free slots slot_ids[n]
+ * (host, 0 <= slot < max_slots, distinct).  Host inputs, copied before
+ * return, [n][row] as for pf_engine_submit.  The inputs reach the device on
+ * `stream` (asynchronously); the scenarios take part from the next
+ * pf_engine_step.  Errors: PF_INVALID_ARG (request-driven engine, slot out of
+ * range, occupied or repeated, null input). */
+pf_status pf_engine_admit(pf_engine* engine, int32_t n, const int32_t* slot_ids, const double* in0,
+                          const double* in1, const double* in2, pf_stream stream);
+/* One step on `stream`: every occupied slot whose scenario has not finished
+ * runs at most `iters` (>= 1) Newton updates or fixed-point iterations.
+ * Waits for the stream, then writes the slots whose scenario finished in this
+ * step (converged, abandoned or out of iterations) to done_slots[*n_done]
+ * (host, capacity max_done, which must be at least the number of unfinished
+ * scenarios, or max_slots), and the number still iterating to *n_active (may
+ * be null).  A finished scenario keeps its slot until harvested.
+ * Errors: PF_INVALID_ARG, PF_HIP_ERROR. */
+pf_status pf_engine_step(pf_engine* engine, int32_t iters, int32_t max_done, int32_t* done_slots,
+                         int32_t* n_done, int32_t* n_active, pf_stream stream);
+/* Copy the results of the finished scenarios in slot_ids[n] to host memory,
+ * [n][...] in that order (v_out complex [n][row], iters, converged,
+ * final_mismatch as for pf_engine_fetch; any output may be null), and free
+ * their slots.  Waits for `stream`.  Errors: PF_INVALID_ARG (a slot not
+ * holding a finished scenario, repeated slot), PF_HIP_ERROR. */
+pf_status pf_engine_harvest(pf_engine* engine, int32_t n, const int32_t* slot_ids, double* v_out,
+                            int32_t* iters, uint8_t* converged, double* final_mismatch, pf_stream stream);
+
+/* Request-driven engines.  Queue request `id` (caller-chosen, unique among
+ * unfetched requests) of n scenarios.  Host inputs, copied before return,
+ * [n][row]: transmission: in0 = p_inj, in1 = q_inj, in2 = vm_set (row =
+ * n_bus, as in pf_tx_solve); feeder: in0 = s_wye, in1 = s_delta complex
+ * (row = 2 n_node doubles, as in pf_dist_solve), in2 unused.
+ * Errors: PF_NOT_ADMITTED (n exceeds the engine's slots), PF_INVALID_ARG
+ * (caller-driven engine, n < 1, duplicate id, null input). */
 pf_status pf_engine_submit(pf_engine* engine, int64_t id, int32_t n, const double* in0, const double* in1,
                            const double* in2);
 /* Ids of up to max_ids finished requests, oldest first, each reported once;
@@ -321,15 +368,16 @@ pf_status pf_engine_request_size(pf_engine* engine, int64_t id, int32_t* n);
 /* Copy a finished request's results to host memory and forget it: v_out
  * complex [n][row] (row = n_bus or n_node), iters[n] (Newton updates or Z-bus
  * iterations), converged[n], final_mismatch[n], times[3] (seconds since the
- * engine was created at submission, launch and completion).  Any output may be
- * null.  Errors: PF_INVALID_ARG (unknown or unfinished id), PF_HIP_ERROR (the
- * request's launch failed; the request is forgotten). */
+ * engine was created: submission, admission into slots, harvest of the last
+ * scenario).  Any output may be null.  Errors: PF_INVALID_ARG (unknown or
+ * unfinished id), PF_HIP_ERROR (a step holding the request's scenarios
+ * failed; the request is forgotten). */
 pf_status pf_engine_fetch(pf_engine* engine, int64_t id, double* v_out, int32_t* iters, uint8_t* converged,
                           double* final_mismatch, double* times);
-/* Counters (any pointer may be null): slots, bytes per slot, requests waiting,
- * launches in flight, launches and scenarios completed. */
+/* Counters (any pointer may be null): slots, bytes per slot, requests waiting
+ * for admission, occupied slots, steps run, scenarios harvested. */
 pf_status pf_engine_info(pf_engine* engine, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued,
-                         int32_t* in_flight, uint64_t* jobs, uint64_t* scenarios);
+                         int32_t* occupied, uint64_t* steps, uint64_t* scenarios);
 
 #ifdef __cplusplus
 }

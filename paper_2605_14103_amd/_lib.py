@@ -34,6 +34,7 @@ class PfOpts(ctypes.Structure):
         ("factor_max_core", c_int32),
         ("zbus_sparse", c_int32),
         ("nr_direct", c_int32),
+        ("step_iters", c_int32),
     ]
 
 
@@ -84,6 +85,9 @@ _SIGS = [
     ("pf_engine_request_size", c_int32, [P, c_int64, I32P]),
     ("pf_engine_fetch", c_int32, [P, c_int64, P, P, P, P, P]),
     ("pf_engine_info", c_int32, [P, I32P, POINTER(c_uint64), I32P, I32P, POINTER(c_uint64), POINTER(c_uint64)]),
+    ("pf_engine_admit", c_int32, [P, c_int32, P, P, P, P, P]),
+    ("pf_engine_step", c_int32, [P, c_int32, c_int32, P, I32P, I32P, P]),
+    ("pf_engine_harvest", c_int32, [P, c_int32, P, P, P, P, P, P]),
 ]
 
 _lib = None

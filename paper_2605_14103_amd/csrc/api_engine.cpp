@@ -124,8 +124,37 @@ pf_status pf_engine_fetch(pf_engine* h, int64_t id, double* v_out, int32_t* iter
 }
 
 pf_status pf_engine_info(pf_engine* h, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued,
-                         int32_t* in_flight, uint64_t* jobs, uint64_t* scenarios) {
-  return guarded([&] { engine_info(engine_of(h), max_slots, slot_bytes, queued, in_flight, jobs, scenarios); });
+                         int32_t* occupied, uint64_t* steps, uint64_t* scenarios) {
+  return guarded([&] { engine_info(engine_of(h), max_slots, slot_bytes, queued, occupied, steps, scenarios); });
+}
+
+pf_status pf_engine_admit(pf_engine* h, int32_t n, const int32_t* slot_ids, const double* in0, const double* in1,
+                          const double* in2, pf_stream stream) {
+  return guarded([&] {
+    Engine* e = engine_of(h);
+    activate(engine_context(e));
+    engine_admit(e, n, slot_ids, in0, in1, in2, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+pf_status pf_engine_step(pf_engine* h, int32_t iters, int32_t max_done, int32_t* done_slots, int32_t* n_done,
+                         int32_t* n_active, pf_stream stream) {
+  return guarded([&] {
+    require(n_done != nullptr, "n_done must not be null");
+    *n_done = 0;
+    Engine* e = engine_of(h);
+    activate(engine_context(e));
+    *n_done = engine_step(e, iters, max_done, done_slots, n_active, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+pf_status pf_engine_harvest(pf_engine* h, int32_t n, const int32_t* slot_ids, double* v_out, int32_t* iters,
+                            uint8_t* converged, double* final_mismatch, pf_stream stream) {
+  return guarded([&] {
+    Engine* e = engine_of(h);
+    activate(engine_context(e));
+    engine_harvest(e, n, slot_ids, v_out, iters, converged, final_mismatch, reinterpret_cast<hipStream_t>(stream));
+  });
 }
 
 }  // extern "C"

@@ -110,11 +110,26 @@ struct ZbusLaunch {
   void* r;            // [rows][Kp] residual in the GEMM's type (rows = batch rounded up to ZB_BM)
   double* st;         // [batch][3]: mismatch, sum |v| at the last residual, change of sum |v|
   int32_t* active;    // [rows] 1 while the scenario still iterates
-  int32_t* count;     // [max_iter + 1] scenarios still active at each iteration
+  int32_t* count;     // [max_iter + 1] scenarios still active at each iteration (may be null)
   int32_t* count_host;  // pinned host copy of `count`, read back by the host loop
+  // Scenario of residual row / workgroup g: slots[g] (null: scenario g).  The
+  // state v, the inputs, outputs, statistics and flags are indexed by the
+  // scenario, the residual rows r by g.  With slots set, each scenario's own
+  // iteration count stands in for the launch's iteration number, and the
+  // residual sets step_done[g] to 1 once the scenario stopped iterating.
+  const int32_t* slots;
+  uint8_t* step_done;
 };
 
 // Runs the whole fixed point on `stream` (host loop over iterations).
 void run_zbus(DistNetwork& net, bool mixed, const ZbusLaunch& a, hipStream_t s);
+
+// Serving-engine pieces over the scenarios a.slots[0 .. a.batch): start them
+// from v0; run `iters` fixed-point iterations (residual, then the update for
+// those still iterating; a.step_done reports the ones that stopped); write
+// the outputs (v_out, final_mismatch) of finished ones.
+void zbus_init_slots(DistNetwork& net, const ZbusLaunch& a, hipStream_t s);
+void zbus_step(DistNetwork& net, bool mixed, const ZbusLaunch& a, int iters, hipStream_t s);
+void zbus_finish_slots(DistNetwork& net, const ZbusLaunch& a, hipStream_t s);
 
 }  // namespace pfx

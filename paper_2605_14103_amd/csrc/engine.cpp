@@ -1,17 +1,29 @@
-// Serving engine: continuous batching of power-flow requests on one network.
+// Serving engine: step-level continuous batching of power-flow scenarios on
+// one network.
 //
-// An engine owns device memory for `max_slots` scenarios (inputs, outputs and
-// solver workspace; the slot count follows from an HBM byte budget) and
-// `n_streams` HIP streams, each driven by a worker thread.  Requests are
-// queued FIFO.  Whenever a worker is idle, the dispatcher packs the longest
-// FIFO prefix of waiting requests that fits a contiguous run of free slots
-// into one job and hands it to that worker, which stages the inputs, launches
-// the batched solve on its stream, copies the results back and frees the
-// slots.  Requests that arrive while other jobs run are therefore admitted as
-// soon as slots and a stream free up, and their kernels run concurrently with
-// the jobs already on the device.  Each scenario is solved by its own
-// workgroup(s) with arithmetic that does not depend on the other scenarios of
-// the job, so a result is bit-identical alone and in the mix.
+// An engine owns device memory for `max_slots` scenarios (inputs, outputs,
+// solver state and workspace; the slot count follows from an HBM byte
+// budget).  A step advances every scenario in the engine's occupied slots by
+// at most a given number of Newton updates (transmission) or fixed-point
+// iterations (feeder) in one launch over the list of those slots.  A scenario
+// resumes exactly where its previous step left it, since its whole state
+// lives in its slot, so its arithmetic, and its result bit for bit, are those
+// of one uninterrupted solve, whatever else shares the steps.  Between steps
+// the scenarios that finished are harvested (results copied out, slots freed)
+// and waiting scenarios are admitted into any free slots.
+//
+// Two ways to drive an engine:
+//  * caller-driven (created with n_streams = 0): pf_engine_admit places
+//    scenarios into chosen free slots, pf_engine_step runs one step on the
+//    caller's stream and returns the slots that finished, pf_engine_harvest
+//    copies their results out and frees them;
+//  * request-driven (n_streams >= 1): requests are queued by
+//    pf_engine_submit; each of n_streams cohorts (a HIP stream and a host
+//    thread) loops over admit -> step -> harvest; all scenarios of a request
+//    join one cohort, and the request is reported by pf_engine_poll once its
+//    last scenario is harvested.  Admission takes requests in arrival order
+//    into any free slots; a request that does not fit yet may be passed by
+//    later ones a bounded number of times.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -19,6 +31,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -32,11 +45,17 @@ namespace pfx {
 
 namespace {
 
+// How many times the oldest waiting request may be passed by later ones
+// before admission waits for it.
+constexpr int kMaxBypass = 8;
+
 struct Request {
   int64_t id = 0;
   int n = 0;
   std::vector<double> in[3];
-  int first = -1;      // first slot while in flight
+  int left = 0;        // scenarios not yet harvested
+  int bypassed = 0;
+  bool admitted = false;
   bool done = false;
   std::string error;
   std::vector<double> v;          // complex interleaved, n rows
@@ -46,20 +65,58 @@ struct Request {
   double t_submit = 0, t_launch = 0, t_done = 0;   // seconds since the engine was created
 };
 
-struct Job {
-  int first = 0, n = 0;
-  std::vector<int64_t> ids;
-};
-
-struct Worker {
+// A stream with the scenarios it steps.  In a caller-driven engine the one
+// cohort runs on the stream each call names.
+struct Cohort {
   hipStream_t stream = nullptr;
   std::thread th;
-  bool busy = false;
-  bool has_job = false;
-  Job job;
-  DeviceBuffer r, count;      // feeder only: residual rows for a whole job, active counts
-  int32_t* count_host = nullptr;
+  std::vector<int> active;   // occupied slots still iterating, in admission order
+  std::vector<int> fresh;    // admitted since the last step
+  DeviceBuffer list_d, fresh_d, harv_d, done_d, r;   // r: feeder residual rows
+  int32_t* list_h = nullptr;
+  int32_t* fresh_h = nullptr;
+  int32_t* harv_h = nullptr;
+  uint8_t* done_h = nullptr;
 };
+
+template <typename T>
+T* host_alloc(size_t count) {
+  void* p = nullptr;
+  PFX_HIP(hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+  std::memset(p, 0, std::max<size_t>(count, 1) * sizeof(T));
+  return static_cast<T*>(p);
+}
+
+uint64_t tx_slot_bytes(const TxNetwork& net, bool mixed, int R) {
+  const uint64_t n = net.n;
+  return 8ull * (3 * n + 2 * n)            // p, q, vm in; v out
+         + 4 + 1 + 8                       // iterations, flag, mismatch
+         + sizeof(NrSlotState)             // resumable Newton state
+         + 8ull * nr_ws_doubles(net)       // FP64 workspace
+         + (uint64_t)(R + 1) * nr_padded_rows(net) * (mixed ? 4 : 8);  // Krylov basis
+}
+
+uint64_t dist_row_bytes(const DistNetwork& net, bool mixed) { return (uint64_t)net.Kp * (mixed ? 4 : 8); }
+
+uint64_t dist_slot_bytes(const DistNetwork& net, bool mixed) {
+  const uint64_t nn = net.n_node;
+  return 16ull * (3 * nn)                  // s_wye, s_delta in; v out
+         + 4 + 1 + 8                       // iterations, flag, mismatch
+         + 8ull * net.Kp + 3 * 8 + 4       // state, statistics, active flag
+         + dist_row_bytes(net, mixed);     // one cohort's residual row
+}
+
+// Calls f(first, count) for each run of consecutive values of sorted `s`.
+template <typename F>
+void for_runs(const std::vector<int>& s, F&& f) {
+  size_t i = 0;
+  while (i < s.size()) {
+    size_t j = i + 1;
+    while (j < s.size() && s[j] == s[j - 1] + 1) ++j;
+    f(s[i], (int)(j - i));
+    i = j;
+  }
+}
 
 }  // namespace
 
@@ -70,12 +127,14 @@ struct Engine {
   DistNetwork* dist = nullptr;
   pf_opts opts{};
   bool mixed = false;
+  bool driven = false;        // request-driven (own cohorts and threads)
   int row = 0;                // reals per scenario row of an input (n_bus, or 2 n_node for complex)
+  int vrow = 0;               // reals per scenario row of the output
   int n_in = 0;
   int max_slots = 0;
   uint64_t per_slot = 0;
   // slot-indexed device buffers
-  DeviceBuffer in_d[3], v_d, iters_d, conv_d, mis_d, ws_d, ws_b, st_d, act_d;
+  DeviceBuffer in_d[3], v_d, iters_d, conv_d, mis_d, ws_d, ws_b, state_d, st_d, act_d;
   int64_t ws_stride = 0, wb_stride = 0;
   // slot-indexed pinned host staging
   double* in_h[3] = {nullptr, nullptr, nullptr};
@@ -83,53 +142,34 @@ struct Engine {
   double* mis_h = nullptr;
   int32_t* iters_h = nullptr;
   uint8_t* conv_h = nullptr;
-  std::vector<char> used;
-  std::vector<Worker> workers;
+  NrSlotState* zero_state_h = nullptr;
+  // slot bookkeeping (under mu): 0 free, 1 iterating, 2 finished and not yet harvested
+  std::vector<int8_t> slot_st;
+  std::vector<int64_t> slot_req;
+  std::vector<int> slot_idx;
+  std::set<int> free_slots;
+  std::vector<Cohort> cohorts;
   std::mutex mu;
-  std::condition_variable cv_dispatch, cv_work, cv_done;
+  std::mutex drive_mu;         // caller-driven calls, one at a time
+  std::condition_variable cv_work, cv_done;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
   std::deque<int64_t> pending;
   std::map<int64_t, Request> reqs;
   std::deque<int64_t> completed;
   bool stop = false;
-  std::thread dispatcher;
-  uint64_t n_jobs = 0, n_scen = 0;
-  int in_flight = 0;
+  uint64_t n_steps = 0, n_scen = 0;
 
   ~Engine();
-  int find_range(int n) const;
-  void dispatch_loop();
-  void worker_loop(int w);
-  void run_job(Worker& wk, const Job& job);
+  void stage_in(Cohort& c, std::vector<int> slots, hipStream_t s);
+  std::vector<int> step(Cohort& c, int iters, hipStream_t s);
+  void collect(Cohort& c, std::vector<int> slots, hipStream_t s);
+  bool can_admit() const;
+  std::vector<int> admit_pending();
+  void complete(const std::vector<int>& slots, const std::string& err);
+  void cohort_loop(int ci);
+  int occupied() const { return max_slots - (int)free_slots.size(); }
 };
-
-namespace {
-
-template <typename T>
-T* host_alloc(size_t count) {
-  void* p = nullptr;
-  PFX_HIP(hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
-  return static_cast<T*>(p);
-}
-
-uint64_t tx_slot_bytes(const TxNetwork& net, bool mixed, int R) {
-  const uint64_t n = net.n;
-  return 8ull * (3 * n + 2 * n)            // p, q, vm in; v out
-         + 4 + 1 + 8                       // iterations, flag, mismatch
-         + 8ull * nr_ws_doubles(net)       // FP64 workspace
-         + (uint64_t)(R + 1) * nr_padded_rows(net) * (mixed ? 4 : 8);  // Krylov basis
-}
-
-uint64_t dist_slot_bytes(const DistNetwork& net, bool mixed) {
-  const uint64_t nn = net.n_node;
-  return 16ull * (3 * nn)                  // s_wye, s_delta in; v out
-         + 4 + 1 + 8                       // iterations, flag, mismatch
-         + 8ull * net.Kp + 3 * 8 + 4       // state, statistics, active flag
-         + (uint64_t)net.Kp * (mixed ? 4 : 8);   // residual row (one per worker, counted per slot)
-}
-
-}  // namespace
 
 uint64_t engine_slot_bytes(int kind, void* net, const pf_opts& o) {
   const bool mixed = o.precision == PF_MIXED;
@@ -140,20 +180,27 @@ uint64_t engine_slot_bytes(int kind, void* net, const pf_opts& o) {
 Engine* engine_create(Context* ctx, int kind, void* network, uint64_t hbm_bytes, int n_streams,
                       const pf_opts& o) {
   require(kind == 0 || kind == 1, "kind must be 0 (transmission) or 1 (feeder)");
-  require(n_streams >= 1 && n_streams <= 8, "n_streams must be 1..8");
+  require(n_streams >= 0 && n_streams <= 8, "n_streams must be 0..8");
   auto e = std::make_unique<Engine>();
   e->ctx = ctx;
   e->kind = kind;
   e->opts = o;
   e->mixed = o.precision == PF_MIXED;
+  e->driven = n_streams > 0;
+  const int n_cohorts = std::max(1, n_streams);
   e->per_slot = engine_slot_bytes(kind, network, o);
-  e->max_slots = (int)std::min<uint64_t>(hbm_bytes / e->per_slot, 1u << 20);
+  // every cohort beyond the first needs its own feeder residual row per slot
+  const uint64_t extra = kind == 1 ? (uint64_t)(n_cohorts - 1) *
+                                         dist_row_bytes(*static_cast<DistNetwork*>(network), e->mixed)
+                                   : 0;
+  e->max_slots = (int)std::min<uint64_t>(hbm_bytes / (e->per_slot + extra), 1u << 20);
   require(e->max_slots >= 1, "HBM budget below one scenario's footprint (" + std::to_string(e->per_slot) + " bytes)");
   const size_t S = e->max_slots;
   if (kind == 0) {
     e->tx = static_cast<TxNetwork*>(network);
     const TxNetwork& net = *e->tx;
     e->row = net.n;
+    e->vrow = 2 * net.n;
     e->n_in = 3;
     for (int i = 0; i < 3; ++i) e->in_d[i].allocate(ctx, S * net.n * 8);
     e->v_d.allocate(ctx, S * net.n * 16);
@@ -161,41 +208,54 @@ Engine* engine_create(Context* ctx, int kind, void* network, uint64_t hbm_bytes,
     e->wb_stride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(net);
     e->ws_d.allocate(ctx, S * e->ws_stride * 8);
     e->ws_b.allocate(ctx, S * e->wb_stride * (e->mixed ? 4 : 8));
+    e->state_d.allocate(ctx, S * sizeof(NrSlotState));
+    e->zero_state_h = host_alloc<NrSlotState>(S);
   } else {
     e->dist = static_cast<DistNetwork*>(network);
     const DistNetwork& net = *e->dist;
     e->row = 2 * net.n_node;
+    e->vrow = 2 * net.n_node;
     e->n_in = 2;
     for (int i = 0; i < 2; ++i) e->in_d[i].allocate(ctx, S * net.n_node * 16);
     e->v_d.allocate(ctx, S * net.n_node * 16);
     e->ws_d.allocate(ctx, S * net.Kp * 8);
     e->st_d.allocate(ctx, S * 3 * 8);
-    e->act_d.allocate(ctx, (S + ZB_BM) * 4);
+    e->act_d.allocate(ctx, S * 4);
   }
   e->iters_d.allocate(ctx, S * 4);
   e->conv_d.allocate(ctx, S);
   e->mis_d.allocate(ctx, S * 8);
-  const int vrow = kind == 0 ? 2 * e->tx->n : 2 * e->dist->n_node;
   for (int i = 0; i < e->n_in; ++i) e->in_h[i] = host_alloc<double>(S * e->row);
-  e->v_h = host_alloc<double>(S * vrow);
+  e->v_h = host_alloc<double>(S * e->vrow);
   e->mis_h = host_alloc<double>(S);
   e->iters_h = host_alloc<int32_t>(S);
   e->conv_h = host_alloc<uint8_t>(S);
-  e->used.assign(S, 0);
-  e->workers.resize(n_streams);
-  for (auto& w : e->workers) {
-    PFX_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking));
+  e->slot_st.assign(S, 0);
+  e->slot_req.assign(S, -1);
+  e->slot_idx.assign(S, 0);
+  for (int s = 0; s < (int)S; ++s) e->free_slots.insert(e->free_slots.end(), s);
+  e->cohorts.resize(n_cohorts);
+  for (auto& c : e->cohorts) {
+    if (e->driven) PFX_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    c.list_d.allocate(ctx, S * 4);
+    c.fresh_d.allocate(ctx, S * 4);
+    c.harv_d.allocate(ctx, S * 4);
+    c.done_d.allocate(ctx, S);
+    c.list_h = host_alloc<int32_t>(S);
+    c.fresh_h = host_alloc<int32_t>(S);
+    c.harv_h = host_alloc<int32_t>(S);
+    c.done_h = host_alloc<uint8_t>(S);
     if (kind == 1) {
+      // rows of the step's residual by list position, padded to the GEMM's
+      // row tile; padding columns must read as zeros
       const size_t rows = (S + ZB_BM - 1) / ZB_BM * ZB_BM;
-      w.r.allocate(ctx, rows * e->dist->Kp * (e->mixed ? 4 : 8));
-      PFX_HIP(hipMemset(w.r.as<void>(), 0, w.r.bytes()));
-      w.count.allocate(ctx, (o.zbus_max_iter + 1) * 4);
-      w.count_host = host_alloc<int32_t>(o.zbus_max_iter + 1);
+      c.r.allocate(ctx, rows * e->dist->Kp * (e->mixed ? 4 : 8));
+      PFX_HIP(hipMemset(c.r.as<void>(), 0, c.r.bytes()));
     }
   }
   Engine* raw = e.get();
-  for (int i = 0; i < n_streams; ++i) raw->workers[i].th = std::thread([raw, i] { raw->worker_loop(i); });
-  raw->dispatcher = std::thread([raw] { raw->dispatch_loop(); });
+  if (raw->driven)
+    for (int i = 0; i < n_cohorts; ++i) raw->cohorts[i].th = std::thread([raw, i] { raw->cohort_loop(i); });
   return e.release();
 }
 
@@ -204,195 +264,251 @@ Engine::~Engine() {
     std::lock_guard<std::mutex> lk(mu);
     stop = true;
   }
-  cv_dispatch.notify_all();
   cv_work.notify_all();
-  if (dispatcher.joinable()) dispatcher.join();
-  for (auto& w : workers)
-    if (w.th.joinable()) w.th.join();
-  for (auto& w : workers) {
-    if (w.stream) (void)hipStreamDestroy(w.stream);
-    if (w.count_host) (void)hipHostFree(w.count_host);
+  for (auto& c : cohorts)
+    if (c.th.joinable()) c.th.join();
+  for (auto& c : cohorts) {
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    for (void* p : {(void*)c.list_h, (void*)c.fresh_h, (void*)c.harv_h, (void*)c.done_h})
+      if (p) (void)hipHostFree(p);
   }
   for (auto* p : in_h)
     if (p) (void)hipHostFree(p);
-  if (v_h) (void)hipHostFree(v_h);
-  if (mis_h) (void)hipHostFree(mis_h);
-  if (iters_h) (void)hipHostFree(iters_h);
-  if (conv_h) (void)hipHostFree(conv_h);
+  for (void* p : {(void*)v_h, (void*)mis_h, (void*)iters_h, (void*)conv_h, (void*)zero_state_h})
+    if (p) (void)hipHostFree(p);
 }
 
-// First run of n consecutive free slots, or -1.
-int Engine::find_range(int n) const {
-  int run = 0;
-  for (int s = 0; s < max_slots; ++s) {
-    run = used[s] ? 0 : run + 1;
-    if (run == n) return s - n + 1;
-  }
-  return -1;
+// Copies the inputs of newly occupied slots (already in the pinned staging
+// rows) to the device and adds the slots to the cohort.
+void Engine::stage_in(Cohort& c, std::vector<int> slots, hipStream_t s) {
+  if (slots.empty()) return;
+  std::sort(slots.begin(), slots.end());
+  for_runs(slots, [&](int first, int cnt) {
+    for (int i = 0; i < n_in; ++i)
+      PFX_HIP(hipMemcpyAsync(in_d[i].as<double>() + (size_t)first * row, in_h[i] + (size_t)first * row,
+                             sizeof(double) * (size_t)cnt * row, hipMemcpyHostToDevice, s));
+    if (kind == 0)
+      PFX_HIP(hipMemcpyAsync(state_d.as<NrSlotState>() + first, zero_state_h + first,
+                             sizeof(NrSlotState) * (size_t)cnt, hipMemcpyHostToDevice, s));
+  });
+  c.active.insert(c.active.end(), slots.begin(), slots.end());
+  c.fresh.insert(c.fresh.end(), slots.begin(), slots.end());
 }
 
-void Engine::dispatch_loop() {
-  (void)hipSetDevice(ctx->device);
-  std::unique_lock<std::mutex> lk(mu);
-  for (;;) {
-    cv_dispatch.wait(lk, [&] {
-      if (stop) return true;
-      if (pending.empty()) return false;
-      for (auto& w : workers)
-        if (!w.busy) return true;
-      return false;
-    });
-    if (stop) return;
-    int wi = -1;
-    for (size_t i = 0; i < workers.size(); ++i)
-      if (!workers[i].busy) {
-        wi = (int)i;
-        break;
-      }
-    // longest FIFO prefix that fits one contiguous free range
-    Job job;
-    int total = 0;
-    size_t take = 0;
-    int first = -1;
-    for (size_t k = 0; k < pending.size(); ++k) {
-      const int n = reqs[pending[k]].n;
-      const int f = find_range(total + n);
-      if (f < 0) break;
-      total += n;
-      first = f;
-      take = k + 1;
-    }
-    if (take == 0) {  // nothing fits now; wait for a job to finish
-      cv_dispatch.wait(lk, [&] { return stop || in_flight == 0 || find_range(reqs[pending.front()].n) >= 0; });
-      continue;
-    }
-    job.first = first;
-    job.n = total;
-    int off = first;
-    for (size_t k = 0; k < take; ++k) {
-      Request& r = reqs[pending.front()];
-      pending.pop_front();
-      r.first = off;
-      r.t_launch = now();
-      for (int i = 0; i < n_in; ++i)
-        std::memcpy(in_h[i] + (size_t)off * row, r.in[i].data(), sizeof(double) * (size_t)r.n * row);
-      for (int q = 0; q < r.n; ++q) used[off + q] = 1;
-      job.ids.push_back(r.id);
-      off += r.n;
-    }
-    Worker& w = workers[wi];
-    w.busy = true;
-    w.has_job = true;
-    w.job = std::move(job);
-    ++in_flight;
-    cv_work.notify_all();
-  }
-}
-
-void Engine::run_job(Worker& wk, const Job& job) {
-  const int first = job.first, n = job.n;
-  const hipStream_t s = wk.stream;
-  for (int i = 0; i < n_in; ++i)
-    PFX_HIP(hipMemcpyAsync(in_d[i].as<double>() + (size_t)first * row, in_h[i] + (size_t)first * row,
-                           sizeof(double) * (size_t)n * row, hipMemcpyHostToDevice, s));
-  size_t vrow = 0;
+// One step over the cohort's occupied slots; returns the slots that finished
+// (removed from the cohort).  Waits for the stream.
+std::vector<int> Engine::step(Cohort& c, int iters, hipStream_t s) {
+  const int n = (int)c.active.size();
+  if (n == 0) return {};
+  std::copy(c.active.begin(), c.active.end(), c.list_h);
+  PFX_HIP(hipMemcpyAsync(c.list_d.as<int32_t>(), c.list_h, 4 * (size_t)n, hipMemcpyHostToDevice, s));
   if (kind == 0) {
     const TxNetwork& net = *tx;
-    vrow = 2 * net.n;
     NRLaunch a{};
     a.batch = n;
     a.ld = net.n;
-    a.p_inj = in_d[0].as<double>() + (size_t)first * net.n;
-    a.q_inj = in_d[1].as<double>() + (size_t)first * net.n;
-    a.vm_set = in_d[2].as<double>() + (size_t)first * net.n;
-    a.v_out = v_d.as<double>() + (size_t)first * vrow;
-    a.newton_iters = iters_d.as<int32_t>() + first;
-    a.gmres_iters = nullptr;
-    a.converged = conv_d.as<uint8_t>() + first;
-    a.final_mismatch = mis_d.as<double>() + first;
-    a.work_bytes = nullptr;
+    a.p_inj = in_d[0].as<double>();
+    a.q_inj = in_d[1].as<double>();
+    a.vm_set = in_d[2].as<double>();
+    a.v_out = v_d.as<double>();
+    a.newton_iters = iters_d.as<int32_t>();
+    a.converged = conv_d.as<uint8_t>();
+    a.final_mismatch = mis_d.as<double>();
     a.tol = opts.tol;
     a.diverge = opts.diverge;
     a.rtol = opts.gmres_rtol;
     a.max_newton = opts.max_newton;
     a.restart = opts.gmres_restart;
     a.max_restarts = opts.gmres_max_restarts;
-    a.ws_d = ws_d.as<double>() + (size_t)first * ws_stride;
+    a.ws_d = ws_d.as<double>();
     a.ws_d_stride = ws_stride;
-    a.ws_basis = ws_b.as<char>() + (size_t)first * wb_stride * (mixed ? 4 : 8);
+    a.ws_basis = ws_b.as<void>();
     a.ws_b_stride = wb_stride;
+    a.slots = c.list_d.as<int32_t>();
+    a.state = state_d.as<NrSlotState>();
+    a.step_iters = iters;
+    a.step_done = c.done_d.as<uint8_t>();
     launch_nr(net, mixed, a, s);
   } else {
     DistNetwork& net = *dist;
-    vrow = 2 * net.n_node;
     ZbusLaunch a{};
-    a.batch = n;
     a.ld = net.n_node;
-    a.s_wye = in_d[0].as<double>() + (size_t)first * row;
-    a.s_delta = in_d[1].as<double>() + (size_t)first * row;
-    a.v_out = v_d.as<double>() + (size_t)first * vrow;
-    a.iters = iters_d.as<int32_t>() + first;
-    a.converged = conv_d.as<uint8_t>() + first;
-    a.final_mismatch = mis_d.as<double>() + first;
-    a.sum_abs_change = nullptr;
+    a.s_wye = in_d[0].as<double>();
+    a.s_delta = in_d[1].as<double>();
+    a.v_out = v_d.as<double>();
+    a.iters = iters_d.as<int32_t>();
+    a.converged = conv_d.as<uint8_t>();
+    a.final_mismatch = mis_d.as<double>();
     a.tol = opts.tol;
     a.max_iter = opts.zbus_max_iter;
     a.sparse = opts.zbus_sparse;
-    a.v = ws_d.as<double>() + (size_t)first * net.Kp;
-    a.r = wk.r.as<void>();
-    a.st = st_d.as<double>() + (size_t)first * 3;
-    a.active = act_d.as<int32_t>() + first;
-    a.count = wk.count.as<int32_t>();
-    a.count_host = wk.count_host;
-    run_zbus(net, mixed, a, s);
+    a.v = ws_d.as<double>();
+    a.r = c.r.as<void>();
+    a.st = st_d.as<double>();
+    a.active = act_d.as<int32_t>();
+    if (!c.fresh.empty()) {
+      std::copy(c.fresh.begin(), c.fresh.end(), c.fresh_h);
+      PFX_HIP(hipMemcpyAsync(c.fresh_d.as<int32_t>(), c.fresh_h, 4 * c.fresh.size(), hipMemcpyHostToDevice, s));
+      a.batch = (int)c.fresh.size();
+      a.slots = c.fresh_d.as<int32_t>();
+      zbus_init_slots(net, a, s);
+    }
+    a.batch = n;
+    a.slots = c.list_d.as<int32_t>();
+    a.step_done = c.done_d.as<uint8_t>();
+    zbus_step(net, mixed, a, iters, s);
   }
-  PFX_HIP(hipMemcpyAsync(v_h + (size_t)first * vrow, v_d.as<double>() + (size_t)first * vrow,
-                         sizeof(double) * (size_t)n * vrow, hipMemcpyDeviceToHost, s));
-  PFX_HIP(hipMemcpyAsync(iters_h + first, iters_d.as<int32_t>() + first, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
-  PFX_HIP(hipMemcpyAsync(conv_h + first, conv_d.as<uint8_t>() + first, (size_t)n, hipMemcpyDeviceToHost, s));
-  PFX_HIP(hipMemcpyAsync(mis_h + first, mis_d.as<double>() + first, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+  c.fresh.clear();
+  PFX_HIP(hipMemcpyAsync(c.done_h, c.done_d.as<uint8_t>(), (size_t)n, hipMemcpyDeviceToHost, s));
+  PFX_HIP(hipStreamSynchronize(s));
+  std::vector<int> done, keep;
+  keep.reserve(n);
+  for (int g = 0; g < n; ++g) (c.done_h[g] ? done : keep).push_back(c.active[g]);
+  c.active.swap(keep);
+  return done;
+}
+
+// Copies the results of finished slots into the pinned staging rows.  Waits
+// for the stream.
+void Engine::collect(Cohort& c, std::vector<int> slots, hipStream_t s) {
+  if (slots.empty()) return;
+  std::sort(slots.begin(), slots.end());
+  if (kind == 1) {
+    DistNetwork& net = *dist;
+    std::copy(slots.begin(), slots.end(), c.harv_h);
+    PFX_HIP(hipMemcpyAsync(c.harv_d.as<int32_t>(), c.harv_h, 4 * slots.size(), hipMemcpyHostToDevice, s));
+    ZbusLaunch a{};
+    a.batch = (int)slots.size();
+    a.ld = net.n_node;
+    a.v_out = v_d.as<double>();
+    a.final_mismatch = mis_d.as<double>();
+    a.v = ws_d.as<double>();
+    a.st = st_d.as<double>();
+    a.slots = c.harv_d.as<int32_t>();
+    zbus_finish_slots(net, a, s);
+  }
+  for_runs(slots, [&](int first, int cnt) {
+    PFX_HIP(hipMemcpyAsync(v_h + (size_t)first * vrow, v_d.as<double>() + (size_t)first * vrow,
+                           sizeof(double) * (size_t)cnt * vrow, hipMemcpyDeviceToHost, s));
+    PFX_HIP(hipMemcpyAsync(iters_h + first, iters_d.as<int32_t>() + first, 4 * (size_t)cnt,
+                           hipMemcpyDeviceToHost, s));
+    PFX_HIP(hipMemcpyAsync(conv_h + first, conv_d.as<uint8_t>() + first, (size_t)cnt, hipMemcpyDeviceToHost, s));
+    PFX_HIP(hipMemcpyAsync(mis_h + first, mis_d.as<double>() + first, 8 * (size_t)cnt, hipMemcpyDeviceToHost, s));
+  });
   PFX_HIP(hipStreamSynchronize(s));
 }
 
-void Engine::worker_loop(int wi) {
+// --------------------------------------------------------- request-driven
+
+bool Engine::can_admit() const {
+  if (pending.empty() || free_slots.empty()) return false;
+  const int nfree = (int)free_slots.size();
+  const Request& head = reqs.at(pending.front());
+  if (head.n <= nfree) return true;
+  if (head.bypassed >= kMaxBypass) return false;
+  for (int64_t id : pending)
+    if (reqs.at(id).n <= nfree) return true;
+  return false;
+}
+
+// Under mu: takes waiting requests, in order, into free slots (lowest first)
+// and stages their inputs in the pinned rows.  Returns the slots taken.
+std::vector<int> Engine::admit_pending() {
+  std::vector<int> taken;
+  auto it = pending.begin();
+  while (it != pending.end() && !free_slots.empty()) {
+    Request& r = reqs.at(*it);
+    const bool head = it == pending.begin();
+    if (r.n > (int)free_slots.size()) {
+      if (head && r.bypassed >= kMaxBypass) break;
+      ++it;
+      continue;
+    }
+    if (!head) {
+      Request& h = reqs.at(pending.front());
+      if (h.bypassed >= kMaxBypass) break;
+      ++h.bypassed;
+    }
+    r.admitted = true;
+    r.t_launch = now();
+    for (int q = 0; q < r.n; ++q) {
+      const int s = *free_slots.begin();
+      free_slots.erase(free_slots.begin());
+      slot_st[s] = 1;
+      slot_req[s] = r.id;
+      slot_idx[s] = q;
+      for (int i = 0; i < n_in; ++i)
+        std::memcpy(in_h[i] + (size_t)s * row, r.in[i].data() + (size_t)q * row, sizeof(double) * row);
+      taken.push_back(s);
+    }
+    for (auto& in : r.in) std::vector<double>().swap(in);
+    it = pending.erase(it);
+  }
+  return taken;
+}
+
+// Under mu: hands the harvested slots' results (pinned rows) to their
+// requests, frees the slots, completes requests whose last scenario this was.
+void Engine::complete(const std::vector<int>& slots, const std::string& err) {
+  const double t = now();
+  for (int s : slots) {
+    Request& r = reqs.at(slot_req[s]);
+    const int q = slot_idx[s];
+    if (err.empty()) {
+      std::memcpy(r.v.data() + (size_t)q * vrow, v_h + (size_t)s * vrow, sizeof(double) * vrow);
+      r.iters[q] = iters_h[s];
+      r.conv[q] = conv_h[s];
+      r.mismatch[q] = mis_h[s];
+    } else if (r.error.empty()) {
+      r.error = err;
+    }
+    slot_st[s] = 0;
+    slot_req[s] = -1;
+    free_slots.insert(s);
+    if (--r.left == 0) {
+      r.done = true;
+      r.t_done = t;
+      completed.push_back(r.id);
+    }
+  }
+  n_scen += slots.size();
+}
+
+void Engine::cohort_loop(int ci) {
   (void)hipSetDevice(ctx->device);
-  Worker& wk = workers[wi];
-  std::unique_lock<std::mutex> lk(mu);
+  Cohort& c = cohorts[ci];
   for (;;) {
-    cv_work.wait(lk, [&] { return stop || wk.has_job; });
-    if (stop) return;
-    Job job = wk.job;
-    wk.has_job = false;
-    lk.unlock();
+    std::vector<int> admitted;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !c.active.empty() || can_admit(); });
+      if (stop) return;
+      admitted = admit_pending();
+    }
+    std::vector<int> done;
     std::string err;
     try {
-      run_job(wk, job);
+      stage_in(c, admitted, c.stream);
+      done = step(c, opts.step_iters, c.stream);
+      collect(c, done, c.stream);
     } catch (const std::exception& e) {
+      // a failed step fails every request with a scenario in this cohort
       err = e.what();
+      done.insert(done.end(), c.active.begin(), c.active.end());
+      c.active.clear();
+      c.fresh.clear();
+      (void)hipStreamSynchronize(c.stream);
     }
-    lk.lock();
-    const size_t vrow = kind == 0 ? 2 * (size_t)tx->n : 2 * (size_t)dist->n_node;
-    for (int64_t id : job.ids) {
-      Request& r = reqs[id];
-      r.error = err;
-      const size_t f = r.first;
-      r.v.assign(v_h + f * vrow, v_h + (f + r.n) * vrow);
-      r.iters.assign(iters_h + f, iters_h + f + r.n);
-      r.conv.assign(conv_h + f, conv_h + f + r.n);
-      r.mismatch.assign(mis_h + f, mis_h + f + r.n);
-      for (int q = 0; q < r.n; ++q) used[f + q] = 0;
-      r.done = true;
-      r.t_done = now();
-      r.first = -1;
-      for (auto& in : r.in) std::vector<double>().swap(in);
-      completed.push_back(id);
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      complete(done, err);
+      ++n_steps;
     }
-    ++n_jobs;
-    n_scen += job.n;
-    --in_flight;
-    wk.busy = false;
-    cv_dispatch.notify_all();
-    cv_done.notify_all();
+    if (!done.empty()) {
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
   }
 }
 
@@ -403,6 +519,7 @@ void* engine_network(const Engine* e) { return e->kind == 0 ? (void*)e->tx : (vo
 Context* engine_context(const Engine* e) { return e->ctx; }
 
 void engine_submit(Engine* e, int64_t id, int n, const double* in0, const double* in1, const double* in2) {
+  require(e->driven, "pf_engine_submit needs a request-driven engine (n_streams >= 1)");
   require(n >= 1, "a request needs at least one scenario");
   if (n > e->max_slots)
     fail(PF_NOT_ADMITTED, "request of " + std::to_string(n) + " scenarios exceeds the engine's " +
@@ -411,18 +528,23 @@ void engine_submit(Engine* e, int64_t id, int n, const double* in0, const double
   Request r;
   r.id = id;
   r.n = n;
+  r.left = n;
   r.t_submit = e->now();
   for (int i = 0; i < e->n_in; ++i) {
     require(ins[i] != nullptr, "null input array");
     r.in[i].assign(ins[i], ins[i] + (size_t)n * e->row);
   }
+  r.v.assign((size_t)n * e->vrow, 0.0);
+  r.iters.assign(n, 0);
+  r.conv.assign(n, 0);
+  r.mismatch.assign(n, 0.0);
   {
     std::lock_guard<std::mutex> lk(e->mu);
     require(!e->reqs.count(id), "request id already in use");
     e->reqs.emplace(id, std::move(r));
     e->pending.push_back(id);
   }
-  e->cv_dispatch.notify_all();
+  e->cv_work.notify_all();
 }
 
 int engine_poll(Engine* e, int max, int64_t* ids, double timeout_s) {
@@ -467,15 +589,97 @@ void engine_fetch(Engine* e, int64_t id, double* v_out, int32_t* iters, uint8_t*
   e->reqs.erase(it);
 }
 
-void engine_info(Engine* e, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued, int32_t* in_flight,
-                 uint64_t* jobs, uint64_t* scenarios) {
+void engine_info(Engine* e, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued, int32_t* occupied,
+                 uint64_t* steps, uint64_t* scenarios) {
   std::lock_guard<std::mutex> lk(e->mu);
   if (max_slots) *max_slots = e->max_slots;
   if (slot_bytes) *slot_bytes = e->per_slot;
   if (queued) *queued = (int32_t)e->pending.size();
-  if (in_flight) *in_flight = e->in_flight;
-  if (jobs) *jobs = e->n_jobs;
+  if (occupied) *occupied = e->occupied();
+  if (steps) *steps = e->n_steps;
   if (scenarios) *scenarios = e->n_scen;
+}
+
+// ---------------------------------------------------------- caller-driven
+
+void engine_admit(Engine* e, int n, const int32_t* slots, const double* in0, const double* in1,
+                  const double* in2, hipStream_t s) {
+  require(!e->driven, "pf_engine_admit needs a caller-driven engine (n_streams = 0)");
+  require(n >= 0, "n must be >= 0");
+  if (n == 0) return;
+  require(slots != nullptr, "null slot list");
+  const double* ins[3] = {in0, in1, in2};
+  for (int i = 0; i < e->n_in; ++i) require(ins[i] != nullptr, "null input array");
+  std::lock_guard<std::mutex> dl(e->drive_mu);
+  std::vector<int> v(slots, slots + n);
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    std::set<int> seen;
+    for (int sl : v) {
+      require(sl >= 0 && sl < e->max_slots, "slot " + std::to_string(sl) + " out of range");
+      require(e->slot_st[sl] == 0, "slot " + std::to_string(sl) + " is occupied");
+      require(seen.insert(sl).second, "slot " + std::to_string(sl) + " listed twice");
+    }
+    for (int q = 0; q < n; ++q) {
+      const int sl = v[q];
+      e->slot_st[sl] = 1;
+      e->free_slots.erase(sl);
+      for (int i = 0; i < e->n_in; ++i)
+        std::memcpy(e->in_h[i] + (size_t)sl * e->row, ins[i] + (size_t)q * e->row, sizeof(double) * e->row);
+    }
+  }
+  e->stage_in(e->cohorts[0], v, s);
+}
+
+int engine_step(Engine* e, int iters, int max_done, int32_t* done_slots, int32_t* n_active, hipStream_t s) {
+  require(!e->driven, "pf_engine_step needs a caller-driven engine (n_streams = 0)");
+  require(iters >= 1, "iters must be >= 1");
+  require(max_done >= 0 && (max_done == 0 || done_slots != nullptr), "bad done-slot output");
+  std::lock_guard<std::mutex> dl(e->drive_mu);
+  Cohort& c = e->cohorts[0];
+  require((int)c.active.size() <= max_done || max_done >= e->max_slots,
+          "max_done must be at least the number of occupied, unfinished slots (" +
+              std::to_string(c.active.size()) + ")");
+  const std::vector<int> done = e->step(c, iters, s);
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    for (int sl : done) e->slot_st[sl] = 2;
+    ++e->n_steps;
+  }
+  std::copy(done.begin(), done.end(), done_slots);
+  if (n_active) *n_active = (int32_t)c.active.size();
+  return (int)done.size();
+}
+
+void engine_harvest(Engine* e, int n, const int32_t* slots, double* v_out, int32_t* iters, uint8_t* conv,
+                    double* mismatch, hipStream_t s) {
+  require(!e->driven, "pf_engine_harvest needs a caller-driven engine (n_streams = 0)");
+  require(n >= 0, "n must be >= 0");
+  if (n == 0) return;
+  require(slots != nullptr, "null slot list");
+  std::lock_guard<std::mutex> dl(e->drive_mu);
+  std::vector<int> v(slots, slots + n);
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    std::set<int> seen;
+    for (int sl : v) {
+      require(sl >= 0 && sl < e->max_slots, "slot " + std::to_string(sl) + " out of range");
+      require(e->slot_st[sl] == 2, "slot " + std::to_string(sl) + " has no finished scenario");
+      require(seen.insert(sl).second, "slot " + std::to_string(sl) + " listed twice");
+    }
+  }
+  e->collect(e->cohorts[0], v, s);
+  std::lock_guard<std::mutex> lk(e->mu);
+  for (int q = 0; q < n; ++q) {
+    const int sl = v[q];
+    if (v_out) std::memcpy(v_out + (size_t)q * e->vrow, e->v_h + (size_t)sl * e->vrow, sizeof(double) * e->vrow);
+    if (iters) iters[q] = e->iters_h[sl];
+    if (conv) conv[q] = e->conv_h[sl];
+    if (mismatch) mismatch[q] = e->mis_h[sl];
+    e->slot_st[sl] = 0;
+    e->free_slots.insert(sl);
+  }
+  e->n_scen += n;
 }
 
 }  // namespace pfx

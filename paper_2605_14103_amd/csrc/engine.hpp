@@ -1,4 +1,4 @@
-// Serving engine (continuous batching over HIP streams); see engine.cpp.
+// Serving engine (step-level continuous batching); see engine.cpp.
 #pragma once
 
 #include <cstdint>
@@ -23,7 +23,13 @@ int engine_poll(Engine* e, int max, int64_t* ids, double timeout_s);
 int engine_request_size(Engine* e, int64_t id);
 void engine_fetch(Engine* e, int64_t id, double* v_out, int32_t* iters, uint8_t* conv, double* mismatch,
                   double* times);
-void engine_info(Engine* e, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued, int32_t* in_flight,
-                 uint64_t* jobs, uint64_t* scenarios);
+void engine_info(Engine* e, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued, int32_t* occupied,
+                 uint64_t* steps, uint64_t* scenarios);
+// Caller-driven engines (n_streams = 0).
+void engine_admit(Engine* e, int n, const int32_t* slots, const double* in0, const double* in1,
+                  const double* in2, hipStream_t s);
+int engine_step(Engine* e, int iters, int max_done, int32_t* done_slots, int32_t* n_active, hipStream_t s);
+void engine_harvest(Engine* e, int n, const int32_t* slots, double* v_out, int32_t* iters, uint8_t* conv,
+                    double* mismatch, hipStream_t s);
 
 }  // namespace pfx

@@ -879,13 +879,19 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   constexpr int NW = BLOCK / WAVE;
   constexpr int K = 2 * KB;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int b = blockIdx.x;
+  const int b = a.slots ? a.slots[blockIdx.x] : (int)blockIdx.x;
   int n, npq, kmax;
   {
     const TxDev<T> net = load_desc(netp);
     n = net.n;
     npq = net.npq;
     kmax = net.bp.k > net.bpp.k ? net.bp.k : net.bpp.k;
+  }
+  NrSlotState* const sst = a.state ? a.state + b : nullptr;
+  const int phase = sst ? sst->phase : 0;
+  if (phase == 2) {  // finished in an earlier launch: nothing to do
+    if (threadIdx.x == 0) a.step_done[blockIdx.x] = 1;
+    return;
   }
   const int R = a.restart;
   const NrLayout L = nr_layout(KB * BLOCK, n - 1, npq, kmax, R, NW, (int)sizeof(T));
@@ -899,7 +905,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
   // flat start: theta = 0, |V| = set-point at PV and slack, 1 at PQ buses;
   // scheduled injections in internal order (padding buses: |V| = 1, no injection)
-  {
+  if (phase == 0) {
     const TxDev<T> net = load_desc(netp);
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
@@ -929,19 +935,44 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   double fnorm = 0.0;
   double work = 0.0;
   int par = 0;
+  // A resumed scenario's workspace already holds the mismatch of its
+  // iterate (tested before it was saved), so it goes straight to the solve.
+  bool resume = phase == 1;
+  if (resume) {
+    newton = sst->newton;
+    gtotal = sst->gtotal;
+    fnorm = sst->fnorm;
+    work = sst->work;
+  }
+  int steps = 0;
   for (;;) {
-    fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW, yv64);
     const TxDev<T> net = load_desc(netp);
     const ByteModel bm{(double)sizeof(T) * net.m, 8.0 * net.m, 8.0 * n, 4.0 * sizeof(T) * n,
                        2.0 * sizeof(T) * a.yv_nnz, 16.0 * a.yv_nnz};
-    work += bm.mismatch();
-    par ^= 1;
-    if (!(fnorm <= a.diverge)) break;
-    if (fnorm <= a.tol) {
-      conv = true;
-      break;
+    if (!resume) {
+      fnorm = mismatch<T, BLOCK, KB>(netp, ws, s.vs, s.redd + par * NW, yv64);
+      work += bm.mismatch();
+      par ^= 1;
+      if (!(fnorm <= a.diverge)) break;
+      if (fnorm <= a.tol) {
+        conv = true;
+        break;
+      }
+      if (newton >= a.max_newton) break;
+      if (sst && steps >= a.step_iters) {
+        // out of this launch's steps: keep the state for the next launch
+        if (threadIdx.x == 0) {
+          sst->phase = 1;
+          sst->newton = newton;
+          sst->gtotal = gtotal;
+          sst->fnorm = fnorm;
+          sst->work = work;
+          a.step_done[blockIdx.x] = 0;
+        }
+        return;
+      }
     }
-    if (newton >= a.max_newton) break;
+    resume = false;
     // right-hand side -F in place (own rows)
 #pragma unroll
     for (int k = 0; k < K; ++k) ws.st(FP, k, -ws.ld(FP, k));
@@ -956,6 +987,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
     work += bm.update();
     ++newton;
+    ++steps;
   }
 
   const Buf vout = make_buf(a.v_out + 2 * (int64_t)b * a.ld);
@@ -981,6 +1013,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     a.converged[b] = conv ? 1 : 0;
     if (a.final_mismatch) a.final_mismatch[b] = fnorm;
     if (a.work_bytes) a.work_bytes[b] = work;
+    if (sst) {
+      sst->phase = 2;
+      a.step_done[blockIdx.x] = 1;
+    }
   }
 }
 

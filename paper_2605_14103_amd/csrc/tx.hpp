@@ -133,6 +133,16 @@ struct TxNetwork {
 // thread (n <= kb * block).
 void nr_shape(int n, int* block, int* kb);
 
+// Resumable per-scenario Newton state of the serving engine's step launches:
+// phase 0 = not started (the next launch begins from the flat start),
+// 1 = between launches (the workspace holds the last iterate, its mismatch F
+// and the V and I planes that mismatch formed; fnorm is max |F|, already
+// tested), 2 = finished (outputs written).
+struct NrSlotState {
+  int32_t phase, newton, gtotal, pad;
+  double fnorm, work;
+};
+
 // Launchers (nr_kernels.hip).
 struct NRLaunch {
   int batch;
@@ -160,6 +170,16 @@ struct NRLaunch {
   const void* yvT;
   int64_t yv_stride;
   double yv_nnz;  // entries counted by the byte model (0 with shared values)
+  // Scenario of each workgroup: slots[g] (null: scenario g).  Every
+  // per-scenario array above is indexed by that scenario.
+  const int32_t* slots;
+  // Step launches (null: one whole solve per launch): each workgroup resumes
+  // its scenario from state[], runs at most step_iters Newton updates and
+  // sets step_done[g] to 1 when the scenario finished (outputs written) or
+  // to 0 when it saved its state for a later launch.
+  NrSlotState* state;
+  int step_iters;
+  uint8_t* step_done;
 };
 
 // Gather per-scenario Ybus values given in the caller's CSR entry order

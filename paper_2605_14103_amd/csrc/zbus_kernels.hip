@@ -57,8 +57,10 @@ __device__ __forceinline__ D2 conj_div(D2 s, double vr, double vi) {
 
 constexpr int WYE_BIT = 1 << 30;
 
+__device__ __forceinline__ int zb_slot(const ZbusLaunch& a, int g) { return a.slots ? a.slots[g] : g; }
+
 __global__ __launch_bounds__(ZB_THREADS) void zb_init(DistDev net, ZbusLaunch a) {
-  const int b = blockIdx.x;
+  const int b = zb_slot(a, blockIdx.x);
   double* v = a.v + (int64_t)b * net.Kp;
   for (int i = threadIdx.x; i < 2 * net.nN; i += ZB_THREADS) v[i] = net.v0[i];
   if (threadIdx.x == 0) {
@@ -83,8 +85,12 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   constexpr int NW = ZB_THREADS / WAVE;
   extern __shared__ D2 vs[];  // [nNs]
   __shared__ double red[2][NW];
-  const int b = blockIdx.x;
-  if (a.active[b] == 0) return;
+  const int g = blockIdx.x;
+  const int b = zb_slot(a, g);
+  if (a.active[b] == 0) {
+    if (a.step_done && threadIdx.x == 0) a.step_done[g] = 1;
+    return;
+  }
   const int nN = net.nN, nNs = net.nNs;
   const double* vrow = a.v + (int64_t)b * net.Kp;
 #pragma unroll
@@ -95,7 +101,7 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   __syncthreads();
   const double* SW = a.s_wye + 2 * (int64_t)b * a.ld;
   const double* SD = a.s_delta + 2 * (int64_t)b * a.ld;
-  T* r = reinterpret_cast<T*>(a.r) + (int64_t)b * net.Kp;
+  T* r = reinterpret_cast<T*>(a.r) + (int64_t)g * net.Kp;
   const int wv = wave_id(), lane = lane_id();
   double mm = 0.0, sabs = 0.0;
 #pragma unroll
@@ -185,10 +191,12 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       mm = nanmax(mm, red[0][w]);
       sabs += red[1][w];
     }
+    if (a.slots) it = a.iters[b];
     double* st = a.st + 3 * (int64_t)b;
     st[0] = mm;
     if (it > 0) st[2] = fabs(sabs - st[1]);
     st[1] = sabs;
+    int more = 0;
     if (mm <= a.tol) {
       a.converged[b] = 1;
       a.active[b] = 0;
@@ -196,8 +204,10 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
       a.active[b] = 0;
     } else {
       a.iters[b] = it + 1;
-      atomicAdd(&a.count[it], 1);
+      more = 1;
+      if (a.count) atomicAdd(&a.count[it], 1);
     }
+    if (a.step_done) a.step_done[g] = more ? 0 : 1;
   }
 }
 
@@ -256,7 +266,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   const int t = threadIdx.x;
   {
     int act = 0;
-    if (t < ZB_BM && row0 + t < a.batch) act = a.active[row0 + t];
+    if (t < ZB_BM && row0 + t < a.batch) act = a.active[zb_slot(a, row0 + t)];
     if (!__syncthreads_or(act)) return;
   }
   const T* R = reinterpret_cast<const T*>(a.r);
@@ -328,8 +338,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
 #pragma unroll
     for (int vv = 0; vv < 4; ++vv) {
       const int row = row0 + wm * 64 + i * 16 + Mfma<T>::out_row(lane, vv);
-      if (row >= a.batch || a.active[row] == 0) continue;
-      double* vrow = a.v + (int64_t)row * Kp;
+      if (row >= a.batch) continue;
+      const int sc = zb_slot(a, row);
+      if (a.active[sc] == 0) continue;
+      double* vrow = a.v + (int64_t)sc * Kp;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int col = col0 + wn * 64 + j * 16 + (lane & 15);
@@ -425,10 +437,11 @@ __global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ __align__(16) unsigned char zsm[];
   T2* u = reinterpret_cast<T2*>(zsm);  // [nN]
-  const int b = blockIdx.x;
+  const int g = blockIdx.x;
+  const int b = zb_slot(a, g);
   if (a.active[b] == 0) return;
   const int nN = net.nN, lane = threadIdx.x;
-  const T2* r = reinterpret_cast<const T2*>(reinterpret_cast<const T*>(a.r) + (int64_t)b * net.Kp);
+  const T2* r = reinterpret_cast<const T2*>(reinterpret_cast<const T*>(a.r) + (int64_t)g * net.Kp);
   constexpr bool f64 = sizeof(T) == 8;
   for (int i = lane; i < nN; i += WAVE) u[cld(net.zf_pinv, (unsigned)i)] = r[i];
   __syncthreads();
@@ -450,7 +463,7 @@ __global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a) {
 
 __global__ __launch_bounds__(ZB_THREADS) void zb_finish(DistDev net, ZbusLaunch a, const int* slack,
                                                        const double* vslack) {
-  const int b = blockIdx.x;
+  const int b = zb_slot(a, blockIdx.x);
   const double* v = a.v + (int64_t)b * net.Kp;
   double* out = a.v_out + 2 * (int64_t)b * a.ld;
   for (int i = threadIdx.x; i < net.nN; i += ZB_THREADS) {
@@ -520,7 +533,52 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
   PFX_HIP(hipGetLastError());
 }
 
+template <typename T>
+void zbus_step_t(DistNetwork& net, const ZbusLaunch& a, int iters, hipStream_t s) {
+  const DistDev d = net.view();
+  const T* W = sizeof(T) == 8 ? net.W64.as<T>() : net.W32.as<T>();
+  const int B = a.batch;
+  const int mt = (B + ZB_BM - 1) / ZB_BM;
+  const int nt = net.Np / ZB_BN;
+  const size_t lds = (size_t)d.nNs * 2 * sizeof(double);
+  const int kb_need = (d.nNs + ZB_THREADS - 1) / ZB_THREADS;
+  auto residual = kb_need <= 1 ? zb_residual<T, 1>
+                  : kb_need <= 2 ? zb_residual<T, 2>
+                  : kb_need <= 4 ? zb_residual<T, 4>
+                  : kb_need <= 8 ? zb_residual<T, 8>
+                                 : zb_residual<T, 16>;
+  for (int k = 0; k < iters; ++k) {
+    hipLaunchKernelGGL(residual, dim3(B), dim3(ZB_THREADS), lds, s, d, a, 0);
+    PFX_HIP(hipGetLastError());
+    if (a.sparse) {
+      hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a);
+    } else {
+      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
+    }
+    PFX_HIP(hipGetLastError());
+  }
+}
+
 }  // namespace
+
+void zbus_init_slots(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
+  if (a.batch == 0) return;
+  hipLaunchKernelGGL(zb_init, dim3(a.batch), dim3(ZB_THREADS), 0, s, net.view(), a);
+  PFX_HIP(hipGetLastError());
+}
+
+void zbus_step(DistNetwork& net, bool mixed, const ZbusLaunch& a, int iters, hipStream_t s) {
+  if (a.batch == 0) return;
+  if (mixed) zbus_step_t<float>(net, a, iters, s);
+  else zbus_step_t<double>(net, a, iters, s);
+}
+
+void zbus_finish_slots(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
+  if (a.batch == 0) return;
+  hipLaunchKernelGGL(zb_finish, dim3(a.batch), dim3(ZB_THREADS), 0, s, net.view(), a, net.slack_d.as<int>(),
+                     net.vslack_d.as<double>());
+  PFX_HIP(hipGetLastError());
+}
 
 void run_zbus(DistNetwork& net, bool mixed, const ZbusLaunch& a, hipStream_t s) {
   if (a.batch == 0) return;

@@ -309,14 +309,17 @@ class EngineResult:
     iters: np.ndarray        # int32 (n,)
     converged: np.ndarray    # uint8 (n,)
     mismatch: np.ndarray     # float64 (n,)
-    times: np.ndarray        # float64 (3,): submitted, launched, completed (s since engine creation)
+    times: np.ndarray        # float64 (3,): submitted, admitted, harvested (s since engine creation)
 
 
 class Engine:
-    """Continuous-batching serving engine over one network; see pf_engine_create.
+    """Step-level continuous-batching serving engine over one network; see
+    pf_engine_create.
 
-    Host numpy arrays in and out: requests arrive from the host, and the engine
-    stages them through its own pinned buffers into device slots.
+    ``n_streams`` >= 1: request-driven (``submit`` / ``poll`` / ``fetch``);
+    ``n_streams`` = 0: caller-driven (``admit`` / ``step`` / ``harvest``).
+    Host numpy arrays in and out: scenarios arrive from the host, and the
+    engine stages them through its own pinned buffers into device slots.
     """
 
     def __init__(self, network, hbm_bytes: int, n_streams: int = 2, **opts):
@@ -332,8 +335,7 @@ class Engine:
         L.call("pf_engine_create", network.ctx.h, tx, dist, int(hbm_bytes), int(n_streams), byref(self._o), byref(h))
         self.h = h
 
-    def submit(self, rid: int, *inputs: np.ndarray) -> None:
-        """Queue request ``rid``: (p, q, vm) float64 (n, n_bus) or (s_wye, s_delta) complex128 (n, n_node)."""
+    def _inputs(self, inputs) -> tuple[int, list, list]:
         want = 3 if self.kind == "tx" else 2
         if len(inputs) != want:
             raise ValueError(f"expected {want} input arrays")
@@ -343,8 +345,39 @@ class Engine:
         for a in arrs:
             if a.shape != (n, self.row):
                 raise ValueError(f"inputs must have shape ({n}, {self.row})")
-        ptrs = [_hptr(a) for a in arrs] + [None] * (3 - want)
+        return n, arrs, [_hptr(a) for a in arrs] + [None] * (3 - want)
+
+    def submit(self, rid: int, *inputs: np.ndarray) -> None:
+        """Queue request ``rid``: (p, q, vm) float64 (n, n_bus) or (s_wye, s_delta) complex128 (n, n_node)."""
+        n, _arrs, ptrs = self._inputs(inputs)
         L.call("pf_engine_submit", self.h, int(rid), n, *ptrs)
+
+    def admit(self, slots, *inputs: np.ndarray, stream=None) -> None:
+        """Caller-driven: place scenarios (inputs as for ``submit``) into free ``slots``."""
+        n, _arrs, ptrs = self._inputs(inputs)
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        if sl.shape != (n,):
+            raise ValueError("one slot per scenario")
+        L.call("pf_engine_admit", self.h, n, _hptr(sl), *ptrs, _stream(stream))
+
+    def step(self, iters: int = 1, stream=None) -> tuple[list[int], int]:
+        """Caller-driven: one step; returns (slots that finished, scenarios still iterating)."""
+        ms = self.info()["max_slots"]
+        done = np.zeros(ms, dtype=np.int32)
+        nd, na = c_int32(), c_int32()
+        L.call("pf_engine_step", self.h, int(iters), ms, _hptr(done), byref(nd), byref(na), _stream(stream))
+        return [int(x) for x in done[: nd.value]], na.value
+
+    def harvest(self, slots, stream=None) -> EngineResult:
+        """Caller-driven: results of finished ``slots`` (in that order); frees the slots."""
+        sl = np.ascontiguousarray(slots, dtype=np.int32)
+        n = int(sl.shape[0])
+        res = EngineResult(v=np.empty((n, self.row), dtype=np.complex128), iters=np.empty(n, dtype=np.int32),
+                           converged=np.empty(n, dtype=np.uint8), mismatch=np.empty(n),
+                           times=np.zeros(3))
+        L.call("pf_engine_harvest", self.h, n, _hptr(sl), _hptr(res.v), _hptr(res.iters), _hptr(res.converged),
+               _hptr(res.mismatch), _stream(stream))
+        return res
 
     def poll(self, max_ids: int = 256, timeout: float = 0.0) -> list[int]:
         ids = np.zeros(max(1, max_ids), dtype=np.int64)
@@ -367,8 +400,8 @@ class Engine:
         ms, q, fl = c_int32(), c_int32(), c_int32()
         sb, jobs, sc = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         L.call("pf_engine_info", self.h, byref(ms), byref(sb), byref(q), byref(fl), byref(jobs), byref(sc))
-        return {"max_slots": ms.value, "slot_bytes": sb.value, "queued": q.value, "in_flight": fl.value,
-                "jobs": jobs.value, "scenarios": sc.value}
+        return {"max_slots": ms.value, "slot_bytes": sb.value, "queued": q.value, "occupied": fl.value,
+                "steps": jobs.value, "scenarios": sc.value}
 
     def close(self) -> None:
         if self.h:

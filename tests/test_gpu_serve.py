@@ -1,5 +1,6 @@
-"""Serving engine on the GPU: admission by HBM footprint, continuous batching
-over several streams, and results identical alone and in the mix."""
+"""Serving engine on the GPU: admission by HBM footprint, step-level continuous
+batching over several streams, caller-driven admit / step / harvest, and
+results identical, bit for bit, to the same scenarios solved alone."""
 import time
 
 import numpy as np
@@ -51,8 +52,8 @@ def _alone_dist(net, sw, sd, **opts):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_tx_alone_equals_mix(ctx, precision):
-    """Requests submitted back to back are packed into shared launches on two
-    streams; every scenario must equal, bit for bit, the same request solved alone."""
+    """Requests submitted back to back share step launches on two streams;
+    every scenario must equal, bit for bit, the same request solved alone."""
     from paper_2605_14103_amd import pf
     say("serve tx30", precision)
     grid = tx.make_grid(tx.TX30)
@@ -67,15 +68,18 @@ def test_tx_alone_equals_mix(ctx, precision):
     got = _collect(eng, list(range(len(reqs))))
     info = eng.info()
     say("after", info)
-    assert info["jobs"] < len(reqs), "requests were not batched together"
+    steps_alone = 0
     for i, b in enumerate(reqs):
         v, it, ok = _alone_tx(net, b.p_inj, b.q_inj, b.vm_set, precision=prec)
+        steps_alone += int(it.max()) + 1
         r = got[i]
         assert r.converged.all() and ok.all()
         assert np.array_equal(r.v.view(np.float64), v.view(np.float64)), f"request {i} differs from alone"
         assert np.array_equal(r.iters, it)
         assert r.mismatch.max() <= 1e-8
         assert r.times[0] <= r.times[1] <= r.times[2]
+    assert info["steps"] < steps_alone, "requests did not share steps"
+    assert info["occupied"] == 0 and info["scenarios"] == sum(sizes)
     # and the mix against the oracle for a few requests
     for i in (1, 4):
         V, _, ok, _ = onr.nr_solve_batch(grid, reqs[i])
@@ -132,12 +136,19 @@ def test_admission_limits_and_lifetime(ctx):
     with pytest.raises(L.PfError) as e:
         eng.submit(0, b.p_inj, b.q_inj, b.vm_set)
     assert e.value.status == L.PF_NOT_ADMITTED
-    # three requests of 3 slots on a 4-slot engine run one after another
+    # three requests of 3 slots on a 4-slot engine: each waits for slots the
+    # one before it frees, and they are admitted in arrival order
     for i in range(3):
         eng.submit(10 + i, b.p_inj[:3], b.q_inj[:3], b.vm_set[:3])
     got = _collect(eng, [10, 11, 12])
     assert all(r.converged.all() for r in got.values())
-    assert eng.info()["jobs"] == 3
+    adm = [got[10 + i].times[1] for i in range(3)]
+    assert adm[0] <= adm[1] <= adm[2]
+    assert got[10].times[1] < got[11].times[1], "the second request was admitted with the first"
+    # the request-driven engine refuses the caller-driven calls
+    with pytest.raises(L.PfError) as e:
+        eng.admit([0], b.p_inj[:1], b.q_inj[:1], b.vm_set[:1])
+    assert e.value.status == L.PF_INVALID_ARG
     eng.submit(20, b.p_inj[:1], b.q_inj[:1], b.vm_set[:1])
     with pytest.raises(L.PfError) as e:
         eng.submit(20, b.p_inj[:1], b.q_inj[:1], b.vm_set[:1])
@@ -250,3 +261,75 @@ def test_full_size_networks_in_one_mix(ctx, precision):
         e.close()
     for n in nets:
         n.close()
+
+
+@pytest.mark.parametrize("kind", ["tx2000", "feeder300"])
+def test_caller_driven_steps(ctx, kind):
+    """Caller-driven engine: scenarios admitted between steps into scattered
+    free slots, one iteration per step, harvested as they finish and their
+    slots reused; every scenario equals its one-shot solve bit for bit."""
+    import torch
+    from paper_2605_14103_amd import _lib as L
+    from paper_2605_14103_amd import pf
+    say("caller-driven", kind)
+    if kind == "tx2000":
+        grid = tx.make_grid(tx.TX2000)
+        net = pf.TxNetwork.from_grid(ctx, grid)
+        batch = tx.make_batch(grid, tx.TX2000, batch=24, seed=77)
+        inputs = [batch.p_inj, batch.q_inj, batch.vm_set]
+        v_ref, it_ref, ok_ref = _alone_tx(net, *inputs)
+    else:
+        fd = fdm.make_feeder(fdm.FEEDER300)
+        net = pf.DistNetwork.from_feeder(ctx, fd)
+        batch = fdm.make_batch(fd, fdm.FEEDER300, batch=24, seed=77)
+        inputs = [batch.s_wye, batch.s_delta]
+        v_ref, it_ref, ok_ref = _alone_dist(net, *inputs)
+    assert ok_ref.all()
+    eng = pf.Engine(net, hbm_bytes=1 << 30, n_streams=0)
+    slots_total = eng.info()["max_slots"]
+    assert slots_total >= 16
+    with pytest.raises(L.PfError) as e:      # caller-driven engines take no requests
+        eng.submit(0, *[a[:1] for a in inputs])
+    assert e.value.status == L.PF_INVALID_ARG
+    stream = torch.cuda.current_stream()
+    # waves of admission: scenario k goes into slot order[k]; later waves
+    # reuse slots freed by earlier ones
+    order = list(range(15, -1, -2)) + list(range(0, 16, 2))
+    waves = [range(0, 5), range(5, 9), range(9, 16), range(16, 24)]
+    free = list(order)
+    where = {}
+    got = {}
+    steps = 0
+    pending_waves = list(waves)
+    with pytest.raises(L.PfError) as e:      # nothing finished yet
+        eng.harvest([0], stream=stream)
+    assert e.value.status == L.PF_INVALID_ARG
+    while pending_waves or where:
+        if pending_waves and len(free) >= len(pending_waves[0]):
+            ks = list(pending_waves.pop(0))
+            sl = [free.pop(0) for _ in ks]
+            eng.admit(sl, *[a[ks] for a in inputs], stream=stream)
+            for k, s_ in zip(ks, sl):
+                where[s_] = k
+            if steps == 0:
+                with pytest.raises(L.PfError) as e:    # an occupied slot
+                    eng.admit([sl[0]], *[a[:1] for a in inputs], stream=stream)
+                assert e.value.status == L.PF_INVALID_ARG
+        done, active = eng.step(1, stream=stream)
+        steps += 1
+        assert steps < 400
+        if done:
+            r = eng.harvest(done, stream=stream)
+            for j, s_ in enumerate(done):
+                k = where.pop(s_)
+                got[k] = (r.v[j], r.iters[j], r.converged[j], r.mismatch[j])
+                free.append(s_)
+    say(f"{kind}: {steps} steps for 24 scenarios in 4 waves, info {eng.info()}")
+    for k in range(24):
+        v, it, ok, mm = got[k]
+        assert ok and mm <= 1e-8
+        assert np.array_equal(v.view(np.float64), v_ref[k].view(np.float64)), f"scenario {k} differs"
+        assert it == it_ref[k]
+    assert eng.info()["occupied"] == 0
+    eng.close()
+    net.close()
