@@ -353,13 +353,21 @@ def test_branch_outages_against_oracle(ctx, precision):
         net = pf.TxNetwork.from_grid(ctx, grid)
         yv = torch.from_numpy(net.ybus_switch(on)).cuda()
         res = _solve_yvals(net, batch, yv, precision=pf.precision(precision))
-        conv = res.converged.cpu().numpy()
+        conv = res.converged.cpu().numpy().astype(bool)
         say(f"{cfg.name} outages {precision}: converged {int(conv.sum())} of {batch.batch}")
-        # the converged scenarios reached the high-voltage solution; the
-        # outages that leave none near flat start report converged = 0
-        assert_high_voltage(res.v.cpu().numpy()[conv.astype(bool)], HV_FLOOR_TX, f"{cfg.name} outages")
-        _check_outages(grid, batch, on, res, np.arange(batch.batch) if cols is None else cols,
-                       f"{cfg.name} {n_out} out {precision}")
+        # Every converged scenario reached the high-voltage solution: those
+        # above the floor by the floor, and the few that an outage leaves
+        # below it (a bus fed over a long path after its line is switched
+        # out) by the oracle's own flat-start solve, element by element.  The
+        # outages that leave no solution near flat start report converged = 0.
+        vmin = np.abs(res.v.cpu().numpy()).min(axis=1)
+        low = np.where(conv & ~(vmin > HV_FLOOR_TX))[0]
+        say(f"{cfg.name} outages {precision}: {len(low)} converged scenarios below {HV_FLOOR_TX} pu: "
+            f"{low.tolist()} at {np.round(vmin[low], 4).tolist()}")
+        assert len(low) <= 8, "more sagging scenarios than the oracle check is sized for"
+        assert_high_voltage(res.v.cpu().numpy()[conv & (vmin > HV_FLOOR_TX)], HV_FLOOR_TX, f"{cfg.name} outages")
+        check = np.arange(batch.batch) if cols is None else np.union1d(cols, low)
+        _check_outages(grid, batch, on, res, check, f"{cfg.name} {n_out} out {precision}")
         net.close()
 
 
