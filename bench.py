@@ -34,38 +34,70 @@ METRIC = "converged PF solves/sec @<=1e-8 pu mismatch, FP64 vs mixed; p50/p99 la
 
 
 # ------------------------------------------------------------------ CPU oracle
+# Forked workers inherit numpy's BLAS thread pool as it was started in the
+# parent, so the thread count is capped through threadpoolctl (environment
+# variables set after numpy is loaded have no effect).
 def _oracle_tx_chunk(args):
     cfg_name, cols = args
-    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
     from oracle import nr
     from workloads import transmission as tx
     cfg = getattr(tx, cfg_name)
     g = tx.make_grid(cfg)
     b = tx.make_batch(g, cfg)
-    t = time.perf_counter()
-    _, _, ok, _ = nr.nr_solve_batch(g, b, columns=np.asarray(cols))
-    return int(ok.sum()), time.perf_counter() - t
+    with threadpool_limits(1):
+        t = time.perf_counter()
+        _, _, ok, _ = nr.nr_solve_batch(g, b, columns=np.asarray(cols))
+        return int(ok.sum()), time.perf_counter() - t
 
 
 def _oracle_feeder_chunk(args):
     cols, = args
-    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
     from oracle import zbus
     from workloads import feeder as fdm
     cfg = fdm.FEEDER300
     fd = fdm.make_feeder(cfg)
     b = fdm.make_batch(fd, cfg)
     sub = fdm.FeederBatch(b.s_wye[cols], b.s_delta[cols])
-    setup = zbus.zbus(fd)   # set-up is excluded from the timing, as on the GPU side
-    t = time.perf_counter()
-    res = zbus.zbus_solve(fd, sub, setup=setup)
-    return int(res.converged.sum()), time.perf_counter() - t
+    with threadpool_limits(1):
+        setup = zbus.zbus(fd)   # set-up is excluded from the timing, as on the GPU side
+        t = time.perf_counter()
+        res = zbus.zbus_solve(fd, sub, setup=setup)
+        return int(res.converged.sum()), time.perf_counter() - t
 
 
-def cpu_baseline(kind: str, n_samples: int, workers: int) -> dict:
-    """Time the oracle on a bounded sample, one scenario chunk per worker process.
+def _oracle_feeder_batched(args):
+    """The feeder oracle on one batch with the host's BLAS threads: the batched
+    product Z @ I over all scenarios at once, the strongest plain-CPU form."""
+    cols, threads = args
+    from threadpoolctl import threadpool_limits
+    from oracle import zbus
+    from workloads import feeder as fdm
+    cfg = fdm.FEEDER300
+    fd = fdm.make_feeder(cfg)
+    b = fdm.make_batch(fd, cfg)
+    sub = fdm.FeederBatch(b.s_wye[cols], b.s_delta[cols])
+    with threadpool_limits(threads):
+        setup = zbus.zbus(fd)
+        t = time.perf_counter()
+        res = zbus.zbus_solve(fd, sub, setup=setup)
+        return int(res.converged.sum()), time.perf_counter() - t
 
-    Runs before the GPU is touched (fork start method)."""
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _pool_leg(kind: str, n_samples: int, workers: int) -> dict:
+    """One leg: n_samples scenarios split over `workers` processes, one core
+    and one BLAS thread each; the rate uses the slowest worker's solve time."""
     cols = np.arange(n_samples)
     chunks = [c.tolist() for c in np.array_split(cols, workers) if len(c)]
     ctxm = mp.get_context("fork")
@@ -78,11 +110,36 @@ def cpu_baseline(kind: str, n_samples: int, workers: int) -> dict:
     wall = time.perf_counter() - t0
     solved = sum(o[0] for o in out)
     busy = max(o[1] for o in out)
-    return {"value": solved / busy, "unit": "solves/s", "cores": len(chunks), "kind": "oracle",
-            "sample": f"{n_samples} scenarios of the same batch, {len(chunks)} worker processes "
-                      f"(one core each, BLAS 1 thread), slowest worker's solve time {busy:.2f} s "
-                      f"(pool wall {wall:.2f} s incl. start-up)",
-            "cpu_seconds": float(sum(o[1] for o in out))}
+    return {"workers": len(chunks), "scenarios": n_samples, "converged": solved, "value": solved / busy,
+            "slowest_worker_s": busy, "pool_wall_s": wall, "cpu_seconds": float(sum(o[1] for o in out))}
+
+
+def cpu_baseline(kind: str, n_samples: int, workers: int) -> dict:
+    """Time the oracle on bounded samples of the workload's batch: a 1-core
+    per-scenario loop, then worker pools of 8, 16 and all usable cores (one
+    core and one BLAS thread per worker, the paper's 1/8/16-worker CPU
+    baselines), and for the feeder also the batched Z @ I product with all
+    cores' BLAS.  The headline value is the largest pool's rate.
+
+    Runs before the GPU is touched (fork start method)."""
+    nproc = os.cpu_count() or 1
+    per_worker = max(1, n_samples // max(1, workers))
+    legs = [_pool_leg(kind, max(4, per_worker), 1)]
+    for w in sorted({min(8, workers), min(16, workers), workers}):
+        if w > 1:
+            legs.append(_pool_leg(kind, per_worker * w, w))
+    if kind == "feeder":
+        ctxm = mp.get_context("fork")
+        with ctxm.Pool(1) as pool:
+            solved, busy = pool.map(_oracle_feeder_batched, [(list(range(n_samples)), workers)])[0]
+        legs.append({"workers": 1, "blas_threads": workers, "scenarios": n_samples, "converged": solved,
+                     "value": solved / busy, "solve_s": busy, "form": "batched Z @ I, all-core BLAS"})
+    main = max((g for g in legs if "blas_threads" not in g), key=lambda g: g["workers"])
+    return {"value": main["value"], "unit": "solves/s", "cores": main["workers"], "kind": "oracle",
+            "sample": f"{main['scenarios']} scenarios of the same batch, {main['workers']} worker processes "
+                      f"(one core each, BLAS 1 thread), slowest worker's solve time "
+                      f"{main['slowest_worker_s']:.2f} s (pool wall {main['pool_wall_s']:.2f} s incl. start-up)",
+            "cpu_seconds": main["cpu_seconds"], "nproc": nproc, "cpu_model": _cpu_model(), "legs": legs}
 
 
 # ------------------------------------------------------------------ GPU timing
@@ -147,7 +204,7 @@ def measured_traffic(profile: str, key: str, family: str = "nr") -> float | None
     return rec.get(key)
 
 
-def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
+def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None, block_jacobi: int = 0) -> dict:
     import torch
 
     from paper_2605_14103_amd import pf
@@ -177,6 +234,25 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
             "algorithmic_bytes_per_launch": work,
             "achieved_GBs": work / (mean_ms * 1e-3) / 1e9,
         }
+    if block_jacobi:
+        # the block-Jacobi reading of the preconditioner (diagonal blocks of 32
+        # buses) against the exact (B' + eps I)^-1, (B'' + eps I)^-1 default
+        net_bj = pf.TxNetwork.from_grid(ctx, grid, precond_block=block_jacobi)
+        for prec in ("fp64", "mixed"):
+            out = net_bj.solve(p, q, vm, precision=pf.precision(prec))
+            ms, wall, out = time_steps(lambda: net_bj.solve(p, q, vm, out=out, precision=pf.precision(prec)),
+                                       steps, warmup)
+            conv = int(out.converged.sum().item())
+            mean_ms = float(ms.mean())
+            runs[f"{prec}_block_jacobi{block_jacobi}"] = {
+                "value": conv / (mean_ms * 1e-3), "ms_per_step": mean_ms, "converged": conv, "batch": B,
+                "newton_iters_mean": float(out.newton_iters.double().mean().item()),
+                "gmres_iters_mean": float(out.gmres_iters.double().mean().item()),
+                "max_mismatch": float(out.mismatch.max().item()),
+                "achieved_GBs": float(out.work_bytes.sum().item()) / (mean_ms * 1e-3) / 1e9}
+            print(f"[bench] {cfg_name} block-Jacobi({block_jacobi}) {prec}: {mean_ms:.3f} ms, "
+                  f"{conv} converged", file=sys.stderr, flush=True)
+        net_bj.close()
     if grid.n_bus <= 800:
         # the direct Newton step (per-scenario sparse LU, FP64) on the same batch
         out = net.solve(p, q, vm, nr_direct=1)
@@ -201,7 +277,9 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
         "metric": METRIC, "value": r["value"], "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{cfg_name}: NR-GMRES(30), {grid.n_bus} buses, batch {B}, flat start, tol 1e-8",
+        "config": {"workload": f"{cfg_name}: NR-GMRES(30) left-preconditioned by the exact (B'+eps I)^-1, "
+                               f"(B''+eps I)^-1 of eqs. (8)-(9), {grid.n_bus} buses, batch {B}, flat start, "
+                               f"tol 1e-8",
                    "global_batch": B, "n_bus": grid.n_bus, "branches": grid.n_branch,
                    "parallelism": "one workgroup per scenario"},
         "latency_ms": r["latency_ms"],
@@ -215,6 +293,7 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None) -> dict:
         "fp64": runs["fp64"], "mixed": runs["mixed"],
         "mixed_vs_fp64": runs["mixed"]["value"] / r["value"],
         "direct": runs.get("fp64_direct"),
+        "block_jacobi": ({k: v for k, v in runs.items() if "block_jacobi" in k} or None),
         "network": net.info,
     }
     if cpu is not None:
@@ -605,6 +684,8 @@ def main() -> int:
                     help="serving: HIP streams of the 30-bus, 2000-bus and feeder engines")
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload: the 2000-bus line alone, without the other configs")
     ap.add_argument("--counters", action="store_true",
                     help="one launch per precision plus a calibration copy, for rocprofv3 --pmc runs")
     a = ap.parse_args()
@@ -616,10 +697,15 @@ def main() -> int:
         return 0
     workers = min(16, os.cpu_count() or 1)
     cpu = None
-    if not a.no_cpu and a.workload in ("tx2000", "tx30", "feeder"):
-        kind = {"tx2000": "TX2000", "tx30": "TX30", "feeder": "feeder"}[a.workload]
-        n_samp = {"tx2000": a.cpu_samples, "tx30": 64, "feeder": 512}[a.workload]
-        cpu = cpu_baseline(kind, n_samp, workers)
+    n_samp = {"tx2000": a.cpu_samples, "tx30": 64, "feeder": 512}
+    kinds = {"tx2000": "TX2000", "tx30": "TX30", "feeder": "feeder"}
+    if not a.no_cpu and a.workload in kinds:
+        cpu = cpu_baseline(kinds[a.workload], n_samp[a.workload], workers)
+    a.sub_cpu = {}
+    if not a.no_cpu and a.workload == "tx2000" and not a.headline_only:
+        # the other configs' oracle legs, also before the GPU is touched
+        for w in ("tx30", "feeder"):
+            a.sub_cpu[w] = cpu_baseline(kinds[w], n_samp[w], workers)
     if a.workload == "feeder":
         line = bench_feeder(a.steps, a.warmup, cpu)
     elif a.workload == "adjoint":
@@ -634,10 +720,40 @@ def main() -> int:
         line = bench_tx_switch(a.steps, a.warmup)
     elif a.workload == "direct_sizes":
         line = bench_direct_sizes(a.steps, a.warmup)
+    elif a.workload == "tx30":
+        line = bench_tx("TX30", a.steps, a.warmup, cpu)
     else:
-        line = bench_tx({"tx2000": "TX2000", "tx30": "TX30"}[a.workload], a.steps, a.warmup, cpu)
+        line = bench_tx("TX2000", a.steps, a.warmup, cpu, block_jacobi=32)
+        if not a.headline_only:
+            line["configs"] = all_configs(a)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _sub(line: dict) -> dict:
+    """A sub-record: the line without the fields that only the headline carries."""
+    return {k: v for k, v in line.items() if k not in ("n_gpus", "scaling", "vs_baseline", "data")}
+
+
+def all_configs(a) -> dict:
+    """The other configurations of the method, each timed as its own line
+    would be, so that one default run measures them all: the 30-bus grid
+    (batch 64), the 900-node feeder (batch 4096, dense product in FP64 and
+    FP32, sparse variant), the adjoint (2000-bus, batch 256) and the serving
+    mix at full and half load."""
+    out = {}
+    for key, fn in (("tx30_b64", lambda: bench_tx("TX30", a.steps, a.warmup, a.sub_cpu.get("tx30"))),
+                    ("feeder300_b4096", lambda: bench_feeder(a.steps, a.warmup, a.sub_cpu.get("feeder"))),
+                    ("adjoint_tx2000_b256", lambda: bench_adjoint(a.steps, a.warmup)),
+                    ("serving_mix", lambda: bench_serving(a.requests, a.lam,
+                                                          tuple(int(x) for x in a.streams.split(","))))):
+        t = time.perf_counter()
+        try:
+            out[key] = _sub(fn())
+        except Exception as e:  # a failing sub-record must not hide the headline
+            out[key] = {"error": f"{type(e).__name__}: {e}"}
+        print(f"[bench] {key}: {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":
