@@ -213,6 +213,38 @@ pf_status pf_tx_ybus_switch(int32_t n_bus, int32_t nnz, const int32_t* row_ptr, 
                             const int32_t* t, const double* r, const double* x, const double* b,
                             int32_t batch, const uint8_t* branch_on, int64_t ldy, double* y_vals);
 
+/* Bytes of the fixed device array behind pf_tx_solve_noalloc (64 MiB). */
+#define PF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* pf_tx_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same results, bit for bit, as pf_tx_solve with
+ * the same arguments, with the per-scenario workspace (Newton state, GMRES
+ * vectors, Krylov basis) taken from one fixed array of
+ * PF_NOALLOC_SCRATCH_BYTES that each device holds from library load until
+ * the process ends.  The call makes no hipMalloc/hipFree or other
+ * allocating call; the caller still provides every input and output as for
+ * pf_tx_solve (all device memory).  The array must hold
+ * align256(batch * 13 nbp * 8) + batch * (gmres_restart + 1) * 2 nbp * w
+ * bytes (nbp = the padded bus count of the kernel's shape, w = 8 for PF_FP64,
+ * 4 for PF_MIXED): on a 2000-bus grid (nbp 2048) about 52 scenarios in FP64
+ * and 99 in mixed precision, on a 30-bus grid about 1700.  The kernels
+ * overwrite every workspace element before reading it, so the array needs
+ * no clearing between calls.  All calls on one device share its array:
+ * the library makes each call's kernels wait on the device for the previous
+ * call's (on whatever stream), so calls enqueued from several streams
+ * serialise rather than corrupt each other; work outside this entry point
+ * never touches the array.  The network's direct Newton step is not
+ * available here (nr_direct must be 0).
+ * Errors: PF_INVALID_ARG (as pf_tx_solve; nr_direct = 1; a batch whose
+ * workspace exceeds the array, with the byte count in the message),
+ * PF_BAD_HANDLE, PF_HIP_ERROR. */
+pf_status pf_tx_solve_noalloc(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
+                              const double* p_inj, const double* q_inj, const double* vm_set,
+                              double* v_out, int32_t* newton_iters, int32_t* gmres_iters,
+                              uint8_t* converged, double* final_mismatch, double* work_bytes,
+                              pf_stream stream);
+
 /* Branch loss L_b = sum over branches of |I_f|^2 with the from-end current
  * I_f = (y_s + j b/2) V_f - y_s V_t, for voltages v (device complex
  * [batch][ld]).  Outputs (device): loss[batch] and, if dl_dv is not null, the

@@ -63,6 +63,8 @@ _SIGS = [
     ("pf_tx_network_info", c_int32, [P, I32P, I32P, I32P, I32P, I32P, I32P, I32P]),
     ("pf_tx_solve", c_int32,
      [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, P, P, P, P, P, P, P]),
+    ("pf_tx_solve_noalloc", c_int32,
+     [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, P, P, P, P, P, P, P]),
     ("pf_tx_solve_yvals", c_int32,
      [P, POINTER(PfOpts), c_int32, c_int64, P, P, P, c_int64, P, P, P, P, P, P, P, P]),
     ("pf_tx_ybus_switch", c_int32,

@@ -141,6 +141,7 @@ pf_status pf_context_create(int32_t device, uint64_t hbm_budget_bytes, pf_contex
     ctx->budget = hbm_budget_bytes;
     PFX_HIP(hipSetDevice(device));
     PFX_HIP(hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device));
+    scratch_init(device);
     registry().add(ctx.get());
     *out = reinterpret_cast<pf_context*>(ctx.release());
   });

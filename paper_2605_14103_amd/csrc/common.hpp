@@ -135,6 +135,10 @@ struct Context {
   std::set<void*> tx_nets, dist_nets, engines;   // owned objects, destroyed with the context
 };
 
+// Take the device address of the no-allocation entry point's fixed scratch
+// array on `device` (current), once per device (noalloc.hip).
+void scratch_init(int device);
+
 // Make the context's device current for the calling thread.
 inline void activate(Context* ctx) { PFX_HIP(hipSetDevice(ctx->device)); }
 

@@ -169,6 +169,22 @@ class TxNetwork:
                _dptr(out.mismatch), _dptr(out.work_bytes), _stream(stream))
         return out
 
+    def solve_noalloc(self, p_inj: torch.Tensor, q_inj: torch.Tensor, vm_set: torch.Tensor, *,
+                      out: TxResult, stream=None, **opts) -> TxResult:
+        """As ``solve``, with the library's workspace taken from its fixed device
+        array (no device allocation in the call); the caller passes every output
+        tensor.  See pf_tx_solve_noalloc."""
+        n = self.n_bus
+        ld = _ld((p_inj, n, torch.float64, "p_inj"), (q_inj, n, torch.float64, "q_inj"),
+                 (vm_set, n, torch.float64, "vm_set"))
+        B = int(p_inj.shape[0])
+        out = self._out(out, B, ld, p_inj.device)
+        o = L.opts(**opts)
+        L.call("pf_tx_solve_noalloc", self.h, byref(o), B, ld, _dptr(p_inj), _dptr(q_inj), _dptr(vm_set),
+               _dptr(out.v), _dptr(out.newton_iters), _dptr(out.gmres_iters), _dptr(out.converged),
+               _dptr(out.mismatch), _dptr(out.work_bytes), _stream(stream))
+        return out
+
     def ybus_switch(self, branch_on: np.ndarray) -> np.ndarray:
         """Per-scenario Ybus values (complex [batch][nnz], this network's CSR
         order) with the branches where ``branch_on`` is 0 switched out; see
