@@ -204,7 +204,8 @@ def measured_traffic(profile: str, key: str, family: str = "nr") -> float | None
     return rec.get(key)
 
 
-def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None, block_jacobi: int = 0) -> dict:
+def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None, block_jacobi: int = 0,
+             direct: bool = True) -> dict:
     import torch
 
     from paper_2605_14103_amd import pf
@@ -253,7 +254,7 @@ def bench_tx(cfg_name: str, steps: int, warmup: int, cpu: dict | None, block_jac
             print(f"[bench] {cfg_name} block-Jacobi({block_jacobi}) {prec}: {mean_ms:.3f} ms, "
                   f"{conv} converged", file=sys.stderr, flush=True)
         net_bj.close()
-    if grid.n_bus <= 800:
+    if direct and grid.n_bus <= 2048:
         # the direct Newton step (per-scenario sparse LU, FP64) on the same batch
         out = net.solve(p, q, vm, nr_direct=1)
         ms, wall, out = time_steps(lambda: net.solve(p, q, vm, out=out, nr_direct=1), steps, warmup)
@@ -318,10 +319,12 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
     B = batch.batch
     nN = net.info["n_free"]
     runs = {}
-    for prec, sparse in (("fp64", 0), ("mixed", 0), ("fp64", 1), ("mixed", 1)):
-        key = prec + ("_sparse" if sparse else "")
-        ms, wall, out = time_steps(lambda: net.solve(sw, sd, precision=pf.precision(prec), zbus_sparse=sparse),
-                                   steps, warmup)
+    for prec, sparse, asy in (("fp64", 0, 0), ("mixed", 0, 0), ("fp64", 1, 0), ("mixed", 1, 0), ("fp64", 0, 1),
+                              ("mixed", 0, 1)):
+        key = prec + ("_sparse" if sparse else "") + ("_async" if asy else "")
+        ms, wall, out = time_steps(
+            lambda: net.solve(sw, sd, precision=pf.precision(prec), zbus_sparse=sparse, zbus_async=asy),
+            steps, warmup)
         conv = int(out.converged.sum().item())
         its = out.iters.double()
         gemm_flops = 8.0 * nN * nN * float(its.sum().item())
@@ -348,6 +351,7 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
                                   "solve time, residual kernels and launch gaps included"},
             "fp64": runs["fp64"], "mixed": runs["mixed"],
             "sparse_variant": {"fp64": runs["fp64_sparse"], "mixed": runs["mixed_sparse"]},
+            "async_enqueue": {"fp64": runs["fp64_async"], "mixed": runs["mixed_async"]},
             "mixed_vs_fp64": runs["mixed"]["value"] / r["value"]}
     if cpu is not None:
         line["cpu_baseline"] = cpu
@@ -685,7 +689,8 @@ def main() -> int:
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
-                    help="default workload: the 2000-bus line alone, without the other configs")
+                    help="default workload: the 2000-bus FP64 and mixed solves alone (no block-Jacobi, "
+                         "direct-step or other-config runs)")
     ap.add_argument("--counters", action="store_true",
                     help="one launch per precision plus a calibration copy, for rocprofv3 --pmc runs")
     a = ap.parse_args()
@@ -723,8 +728,10 @@ def main() -> int:
     elif a.workload == "tx30":
         line = bench_tx("TX30", a.steps, a.warmup, cpu)
     else:
-        line = bench_tx("TX2000", a.steps, a.warmup, cpu, block_jacobi=32)
-        if not a.headline_only:
+        if a.headline_only:
+            line = bench_tx("TX2000", a.steps, a.warmup, cpu, direct=False)
+        else:
+            line = bench_tx("TX2000", a.steps, a.warmup, cpu, block_jacobi=32)
             line["configs"] = all_configs(a)
     print(json.dumps(line), flush=True)
     return 0

@@ -24,7 +24,10 @@
  *     (b, i) at [2 * (b * ld + i)].  ld >= the row length (n_bus or n_node).
  *   - Work is enqueued on the given stream and is asynchronous; outputs are
  *     valid once the stream has been synchronised.  A null stream means the
- *     default stream.
+ *     default stream.  Exceptions, stated with each call: pf_dist_solve
+ *     waits on the host once per fixed-point iteration unless
+ *     opts->zbus_async = 1, and the serving engine's step and harvest calls
+ *     wait for their stream.
  *   - Non-convergence of a scenario is not an error: it is reported through
  *     that scenario's converged flag, iteration count and final mismatch.
  */
@@ -77,11 +80,19 @@ typedef struct pf_opts {
   int32_t zbus_sparse;        /* 0: dense product Z r on the matrix cores (default); 1: Y_NN^-1 r
                                  by level-scheduled solves with a sparse L D L^T of Y_NN (the
                                  sparse variant named as future work in Sec. II-B) */
+  int32_t zbus_async;         /* 0: the host reads each iteration's active count back and stops
+                                 enqueuing once none is left, waiting one iteration behind the
+                                 device (default); 1: all zbus_max_iter iterations are enqueued
+                                 at once and exit on the device once no scenario is active, so
+                                 the call returns without waiting (each exited iteration still
+                                 costs its two launches, about 3.6 us) */
   /* transmission Newton step */
   int32_t nr_direct;          /* 0: preconditioned GMRES (default); 1: exact Newton step by a
                                  per-scenario sparse LU of J on a shared symbolic analysis (the
                                  sparse direct outlook of Sec. IV), always in FP64, for networks
-                                 whose factor fits the per-scenario limit (12288 values) */
+                                 of up to 2048 buses; the factor lives in LDS when it fits, else
+                                 in network-owned device memory (8 bytes per factor value and
+                                 scenario of the batch) */
   /* serving engine */
   int32_t step_iters;         /* Newton updates or fixed-point iterations per engine step of a
                                  request-driven engine, 1..1000, default 1 */
@@ -165,8 +176,8 @@ pf_status pf_tx_network_info(const pf_tx_network* net, int32_t* n_bus, int32_t* 
  * With opts->nr_direct = 1 each Newton step is solved exactly by a sparse LU
  * of J (FP64 whatever opts->precision says; gmres_iters reports 0; the
  * byte model counts the mismatch plus 40m per step); the network's shared
- * analysis is built on the first such call, and a network whose factor
- * exceeds the per-scenario limit is refused with PF_INVALID_ARG.
+ * analysis is built on the first such call, and a network above 2048 buses
+ * is refused with PF_INVALID_ARG.
  * Errors: PF_INVALID_ARG (ld < n_bus, batch < 0, bad options),
  * PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_tx_solve(pf_tx_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
@@ -305,7 +316,17 @@ pf_status pf_dist_network_info(const pf_dist_network* net, int32_t* n_node, int3
  * max |v * conj(r)| <= tol.  Device outputs: v_out complex [batch][ld] (all
  * nodes, slack included), iters[batch], converged[batch], final_mismatch
  * [batch] (may be null), sum_abs_change[batch] (the change of sum |v| over the
- * last update, the paper's stop quantity; may be null).
+ * last update, the paper's stop quantity; may be null).  By default
+ * (opts->zbus_async = 0) the call blocks the calling thread: it waits on
+ * the host for each iteration's active count, one iteration behind the
+ * device, and stops enqueuing after the last active iteration, returning
+ * once the remaining work (the last update and the output kernel) is
+ * enqueued.  With zbus_async = 1 it enqueues all zbus_max_iter iterations
+ * and returns without waiting; once no scenario is active the remaining
+ * launches exit at once on the device, at about 3.6 us per iteration (with
+ * the default cap of 100 and solves converging in about 5 iterations that
+ * costs 12-20 % of a 900-node batch of 4096; lower zbus_max_iter to cut it).
+ * Caps above 1000 iterations always take the host-checked loop.
  * Errors: PF_INVALID_ARG, PF_OUT_OF_MEMORY, PF_HIP_ERROR. */
 pf_status pf_dist_solve(pf_dist_network* net, const pf_opts* opts, int32_t batch, int64_t ld,
                         const double* s_wye, const double* s_delta, double* v_out, int32_t* iters,

@@ -33,6 +33,7 @@ class PfOpts(ctypes.Structure):
         ("factor_max_levels", c_int32),
         ("factor_max_core", c_int32),
         ("zbus_sparse", c_int32),
+        ("zbus_async", c_int32),
         ("nr_direct", c_int32),
         ("step_iters", c_int32),
     ]

@@ -76,6 +76,7 @@ pf_opts resolve_opts(const pf_opts* o) {
   require(r.factor_max_core >= 0 && r.factor_max_core <= 2048, "factor_max_core must be 0..2048");
   require(r.zbus_sparse == 0 || r.zbus_sparse == 1, "zbus_sparse must be 0 or 1");
   require(r.nr_direct == 0 || r.nr_direct == 1, "nr_direct must be 0 or 1");
+  require(r.zbus_async == 0 || r.zbus_async == 1, "zbus_async must be 0 or 1");
   require(r.step_iters >= 1 && r.step_iters <= 1000, "step_iters must be 1..1000");
   return r;
 }
@@ -124,6 +125,7 @@ void pf_opts_default(pf_opts* o) {
   o->factor_max_core = 384;
   o->zbus_sparse = 0;
   o->nr_direct = 0;
+  o->zbus_async = 0;
   o->step_iters = 1;
 }
 

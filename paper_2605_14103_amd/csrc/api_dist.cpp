@@ -151,7 +151,7 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     net->order.grow(net->ws_s, net->ctx, (size_t)batch * 3 * sizeof(double));
     net->order.grow(net->ws_act, net->ctx, (size_t)rows * sizeof(int32_t));
     net->order.grow(net->ws_cnt, net->ctx, (size_t)(o.zbus_max_iter + 1) * sizeof(int32_t));
-    if (net->count_host_len < o.zbus_max_iter + 1) {
+    if ((!o.zbus_async || o.zbus_max_iter > ZB_ASYNC_MAX_ITER) && net->count_host_len < o.zbus_max_iter + 1) {
       net->order.drain();
       if (net->count_host) PFX_HIP(hipHostFree(net->count_host));
       net->count_host = nullptr;
@@ -172,6 +172,7 @@ pf_status pf_dist_solve(pf_dist_network* h, const pf_opts* opts, int32_t batch, 
     a.tol = o.tol;
     a.max_iter = o.zbus_max_iter;
     a.sparse = o.zbus_sparse;
+    a.async = o.zbus_async;
     a.v = net->ws_v.as<double>();
     a.r = net->ws_r.as<void>();
     a.st = net->ws_s.as<double>();

@@ -127,6 +127,8 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   const int64_t dstride = nr_ws_doubles(*net);
   const int64_t bstride = (int64_t)(o.gmres_restart + 1) * nr_padded_rows(*net);
   net->order.grow(net->ws_d, net->ctx, (size_t)batch * dstride * sizeof(double));
+  const bool dval = direct && !direct_lds_fits(*net);
+  if (dval) net->order.grow(net->ws_dval, net->ctx, (size_t)batch * net->direct_nval * sizeof(double));
   if (!direct)
     net->order.grow(net->ws_basis, net->ctx, (size_t)batch * bstride * (mixed ? sizeof(float) : sizeof(double)));
   net->order.begin(hs);
@@ -164,6 +166,10 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   a.ws_d_stride = dstride;
   a.ws_basis = net->ws_basis.as<void>();
   a.ws_b_stride = bstride;
+  if (dval) {
+    a.ws_dval = net->ws_dval.as<double>();
+    a.ws_dval_stride = net->direct_nval;
+  }
   if (direct) launch_nr_direct(*net, a, hs);
   else launch_nr(*net, mixed, a, hs);
   net->order.end(hs);

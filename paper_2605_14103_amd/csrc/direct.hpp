@@ -38,9 +38,10 @@ struct DirectLuHost {
   std::vector<int> je;       // J entries, 4 ints each: (value index | kind << 28, bus i, bus k, Ybus layout index)
 };
 
-// Values of the factor held per scenario beyond which the direct step is
-// refused (they live in LDS during the factorisation).
-constexpr int DIRECT_MAX_VALUES = 12288;
+// Factor values per scenario beyond which the direct step is refused (the
+// factor lives in LDS when it fits there, else in network-owned device
+// memory, DIRECT_MAX_VALUES doubles per scenario of a batch).
+constexpr int DIRECT_MAX_VALUES = 1 << 22;
 
 // Builds the analysis for a registered network.  Throws PfError
 // (PF_INVALID_ARG) when the factor would exceed DIRECT_MAX_VALUES values.

@@ -91,6 +91,8 @@ constexpr int ZB_MAX_FREE = 4096;   // free nodes (the residual keeps v in LDS)
 constexpr int ZB_BM = 128;   // scenarios per tile
 constexpr int ZB_BN = 128;   // output reals per tile
 constexpr int ZB_BK = 16;    // K step
+// Iteration caps up to this many are enqueued at once in the asynchronous mode.
+constexpr int ZB_ASYNC_MAX_ITER = 1000;
 
 struct ZbusLaunch {
   int batch;
@@ -105,6 +107,7 @@ struct ZbusLaunch {
   double tol;
   int max_iter;
   int sparse;         // 1: v += Y_NN^-1 r by the sparse factor instead of the dense product
+  int async;          // 1: every iteration enqueued at once (kernels exit once count[] shows none active)
   // workspace
   double* v;          // [rows][Kp] FP64 state
   void* r;            // [rows][Kp] residual in the GEMM's type (rows = batch rounded up to ZB_BM)

@@ -1046,7 +1046,10 @@ __host__ __device__ inline size_t direct_stage_bytes(const DirectDev& d) {
 // STAGE: the schedule tables (targets, contributions, J entries, S(k) and the
 // level lists) are copied into LDS once per workgroup, so each phase reads
 // them at LDS latency instead of an L2 round trip (when they fit).
-template <int BLOCK, int KB, bool STAGE>
+// VG: the factor values live in device memory (a.ws_dval, per scenario)
+// instead of LDS, for factors larger than the LDS can hold; the level
+// barriers order their reads and writes within the workgroup as before.
+template <int BLOCK, int KB, bool STAGE, bool VG>
 __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* __restrict__ netp, DirectDev d,
                                                           NRLaunch a) {
   constexpr int NW = BLOCK / WAVE;
@@ -1064,9 +1067,9 @@ __global__ __launch_bounds__(BLOCK) void nr_direct_kernel(const TxDev<double>* _
   double2* vs = reinterpret_cast<double2*>(smem);
   double2* is = vs + NBP;
   double* red = reinterpret_cast<double*>(is + NBP);
-  double* val = red + 2 * NW;
-  double* rhs = val + d.n_val;
+  double* rhs = red + 2 * NW + (VG ? 0 : d.n_val);
   double* xs = rhs + m;
+  double* val = VG ? a.ws_dval + (int64_t)b * a.ws_dval_stride : red + 2 * NW;
   int4 *ltg = nullptr, *lct = nullptr, *lje = nullptr;
   int *lso = nullptr, *lsi = nullptr, *lbr = nullptr, *lfp = nullptr, *lbp = nullptr;
   if constexpr (STAGE) {
@@ -1513,15 +1516,28 @@ struct NrDirectGo {
   void operator()() const {
     const DirectDev& d = net.direct;
     const size_t lds0 = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
-    if (lds0 > 160 * 1024)
-      fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(lds0) + " bytes of LDS)");
+    if (lds0 > 160 * 1024) {
+      // factor values in device memory; V, I, the right-hand side and x stay in LDS
+      const size_t ldsg = (size_t)2 * KB * BLOCK * 16 + 2 * (BLOCK / WAVE) * 8 + (size_t)2 * d.m * 8;
+      if (ldsg > 160 * 1024)
+        fail(PF_INVALID_ARG, "network too large for the direct Newton step (" + std::to_string(ldsg) +
+                                 " bytes of LDS)");
+      if (!a.ws_dval) fail(PF_INVALID_ARG, "direct Newton step without its factor workspace");
+      auto kernel = nr_direct_kernel<BLOCK, KB, false, true>;
+      if (ldsg > 64 * 1024)
+        PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsg));
+      hipLaunchKernelGGL(kernel, dim3(a.batch), dim3(BLOCK), ldsg, s, net.desc<double>(), d, a);
+      PFX_HIP(hipGetLastError());
+      return;
+    }
     // stage the schedule tables when the total stays within 64 KB, or, when
     // the batch has no more scenarios than the chip has CUs (one workgroup
     // per CU, occupancy moot), within the CU's 160 KB
     const size_t lds1 = direct_stage_offset(KB * BLOCK, BLOCK / WAVE, d) + direct_stage_bytes(d);
     const bool stage = lds1 <= (a.batch <= net.ctx->cu_count ? 160 : 64) * 1024;
     const size_t lds = stage ? lds1 : lds0;
-    auto kernel = stage ? nr_direct_kernel<BLOCK, KB, true> : nr_direct_kernel<BLOCK, KB, false>;
+    auto kernel = stage ? nr_direct_kernel<BLOCK, KB, true, false> : nr_direct_kernel<BLOCK, KB, false, false>;
     if (lds > 64 * 1024)
       PFX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1587,6 +1603,12 @@ void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t 
   if (a.batch == 0) return;
   if (mixed) dispatch_shape(net.n, NrGo<float>{net, a, s});
   else dispatch_shape(net.n, NrGo<double>{net, a, s});
+}
+
+bool direct_lds_fits(const TxNetwork& net) {
+  const DirectDev& d = net.direct;
+  const size_t lds0 = (size_t)2 * net.nbp * 16 + 2 * (net.block / WAVE) * 8 + ((size_t)d.n_val + 2 * d.m) * 8;
+  return lds0 <= 160 * 1024;
 }
 
 void launch_nr_direct(const TxNetwork& net, const NRLaunch& a, hipStream_t s) {

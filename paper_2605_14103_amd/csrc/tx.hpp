@@ -117,7 +117,7 @@ struct TxNetwork {
   DirectDev direct{};
   DeviceBuffer dl_fpos, dl_soff, dl_sidx, dl_fph, dl_ftg, dl_fct, dl_bph, dl_brow, dl_je;
   // solve workspaces (grow-only), shared by the network's calls and ordered by `order`
-  DeviceBuffer ws_d, ws_basis, ws_adj, ws_y;
+  DeviceBuffer ws_d, ws_basis, ws_adj, ws_y, ws_dval;
   CallOrder order;
   // the device views themselves, resident in device memory so kernels take one pointer
   DeviceBuffer desc64, desc32;
@@ -180,6 +180,10 @@ struct NRLaunch {
   NrSlotState* state;
   int step_iters;
   uint8_t* step_done;
+  // Direct Newton step whose factor does not fit LDS: each scenario's factor
+  // values at ws_dval + b * ws_dval_stride (device memory).
+  double* ws_dval;
+  int64_t ws_dval_stride;
 };
 
 // Gather per-scenario Ybus values given in the caller's CSR entry order
@@ -193,8 +197,11 @@ void launch_y_gather(const TxNetwork& net, int batch, int64_t ldy, const double*
 int64_t nr_ws_doubles(const TxNetwork& net);
 int64_t nr_padded_rows(const TxNetwork& net);
 void launch_nr(const TxNetwork& net, bool mixed, const NRLaunch& a, hipStream_t s);
-// Direct Newton step (FP64), after ensure_direct(net).
+// Direct Newton step (FP64), after ensure_direct(net).  direct_lds_fits:
+// whether the factor values fit the kernel's LDS (otherwise the launch needs
+// a.ws_dval with net.direct_nval doubles per scenario).
 void ensure_direct(TxNetwork& net);
+bool direct_lds_fits(const TxNetwork& net);
 void launch_nr_direct(const TxNetwork& net, const NRLaunch& a, hipStream_t s);
 
 struct LossLaunch {

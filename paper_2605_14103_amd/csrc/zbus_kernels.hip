@@ -63,6 +63,10 @@ __global__ __launch_bounds__(ZB_THREADS) void zb_init(DistDev net, ZbusLaunch a)
   const int b = zb_slot(a, blockIdx.x);
   double* v = a.v + (int64_t)b * net.Kp;
   for (int i = threadIdx.x; i < 2 * net.nN; i += ZB_THREADS) v[i] = net.v0[i];
+  // the per-iteration active counts start at zero (a fill here rather than a
+  // memset node, so the solve can be captured into a graph)
+  if (blockIdx.x == 0 && a.count)
+    for (int i = threadIdx.x; i <= a.max_iter; i += ZB_THREADS) a.count[i] = 0;
   if (threadIdx.x == 0) {
     a.active[b] = 1;
     a.iters[b] = 0;
@@ -86,6 +90,9 @@ __global__ __launch_bounds__(ZB_THREADS) __attribute__((amdgpu_waves_per_eu(8)))
   extern __shared__ D2 vs[];  // [nNs]
   __shared__ double red[2][NW];
   const int g = blockIdx.x;
+  // whole-batch solves: nothing to do once the previous iteration left no
+  // scenario active (all iterations may be enqueued at once)
+  if (a.count && it > 0 && a.count[it - 1] == 0) return;
   const int b = zb_slot(a, g);
   if (a.active[b] == 0) {
     if (a.step_done && threadIdx.x == 0) a.step_done[g] = 1;
@@ -249,7 +256,7 @@ constexpr int ZB_PAD = 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zb_gemm(
-    DistDev net, const T* __restrict__ W, ZbusLaunch a) {
+    DistDev net, const T* __restrict__ W, ZbusLaunch a, int it) {
   using V4 = typename Mfma<T>::V4;
   const int Kp = net.Kp, Np = net.Np;
   __shared__ T As[2][ZB_BK][ZB_BM + ZB_PAD];
@@ -264,6 +271,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   const int tile_n = lin % nt, tile_m = lin / nt;
   const int row0 = tile_m * ZB_BM, col0 = tile_n * ZB_BN;
   const int t = threadIdx.x;
+  if (a.count && a.count[it] == 0) return;  // no scenario left active (uniform)
   {
     int act = 0;
     if (t < ZB_BM && row0 + t < a.batch) act = a.active[zb_slot(a, row0 + t)];
@@ -433,10 +441,11 @@ __device__ __forceinline__ void zf_solve(typename Vec2<T>::type* u, int nq, cons
 // (FP32 in mixed mode, the FP64 residual then refines the result as for the
 // dense product).
 template <typename T>
-__global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a) {
+__global__ __launch_bounds__(WAVE) void zb_sparse(DistDev net, ZbusLaunch a, int it) {
   using T2 = typename Vec2<T>::type;
   extern __shared__ __align__(16) unsigned char zsm[];
   T2* u = reinterpret_cast<T2*>(zsm);  // [nN]
+  if (a.count && a.count[it] == 0) return;  // no scenario left active
   const int g = blockIdx.x;
   const int b = zb_slot(a, g);
   if (a.active[b] == 0) return;
@@ -498,36 +507,50 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
                                  : zb_residual<T, 16>;
   hipLaunchKernelGGL(zb_init, dim3(B), dim3(ZB_THREADS), 0, s, d, a);
   PFX_HIP(hipGetLastError());
-  PFX_HIP(hipMemsetAsync(a.count, 0, sizeof(int32_t) * (a.max_iter + 1), s));
-  hipEvent_t ev[2];
-  PFX_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  PFX_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  try {
+  auto update = [&](int it) {
+    if (a.sparse) {
+      hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a, it);
+    } else {
+      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a, it);
+    }
+    PFX_HIP(hipGetLastError());
+  };
+  if (a.async && a.max_iter <= ZB_ASYNC_MAX_ITER) {
+    // Every iteration enqueued at once: each kernel first reads the active
+    // count its predecessor left and exits when it is zero, so the host
+    // never waits and the iterations after convergence cost only their
+    // launches.
     for (int it = 0; it <= a.max_iter; ++it) {
       hipLaunchKernelGGL(residual, dim3(B), dim3(ZB_THREADS), lds, s, d, a, it);
       PFX_HIP(hipGetLastError());
-      PFX_HIP(hipMemcpyAsync(a.count_host + it, a.count + it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      PFX_HIP(hipEventRecord(ev[it & 1], s));
-      // Look one iteration back: once no scenario was active, nothing later can be.
-      if (it > 0) {
-        PFX_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-        if (a.count_host[it - 1] == 0) break;
-      }
-      if (it == a.max_iter) break;
-      if (a.sparse) {
-        hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a);
-      } else {
-        hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
-      }
-      PFX_HIP(hipGetLastError());
+      if (it < a.max_iter) update(it);
     }
-  } catch (...) {
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    throw;
+  } else {
+    hipEvent_t ev[2];
+    PFX_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    PFX_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    try {
+      for (int it = 0; it <= a.max_iter; ++it) {
+        hipLaunchKernelGGL(residual, dim3(B), dim3(ZB_THREADS), lds, s, d, a, it);
+        PFX_HIP(hipGetLastError());
+        PFX_HIP(hipMemcpyAsync(a.count_host + it, a.count + it, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        PFX_HIP(hipEventRecord(ev[it & 1], s));
+        // Look one iteration back: once no scenario was active, nothing later can be.
+        if (it > 0) {
+          PFX_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
+          if (a.count_host[it - 1] == 0) break;
+        }
+        if (it == a.max_iter) break;
+        update(it);
+      }
+    } catch (...) {
+      (void)hipEventDestroy(ev[0]);
+      (void)hipEventDestroy(ev[1]);
+      throw;
+    }
+    PFX_HIP(hipEventDestroy(ev[0]));
+    PFX_HIP(hipEventDestroy(ev[1]));
   }
-  PFX_HIP(hipEventDestroy(ev[0]));
-  PFX_HIP(hipEventDestroy(ev[1]));
   hipLaunchKernelGGL(zb_finish, dim3(B), dim3(ZB_THREADS), 0, s, d, a, net.slack_d.as<int>(),
                      net.vslack_d.as<double>());
   PFX_HIP(hipGetLastError());
@@ -551,9 +574,9 @@ void zbus_step_t(DistNetwork& net, const ZbusLaunch& a, int iters, hipStream_t s
     hipLaunchKernelGGL(residual, dim3(B), dim3(ZB_THREADS), lds, s, d, a, 0);
     PFX_HIP(hipGetLastError());
     if (a.sparse) {
-      hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a);
+      hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a, 0);
     } else {
-      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a);
+      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a, 0);
     }
     PFX_HIP(hipGetLastError());
   }

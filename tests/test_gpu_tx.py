@@ -449,14 +449,47 @@ def test_direct_newton_with_branch_outages(ctx):
     net.close()
 
 
-def test_direct_newton_refuses_a_network_too_large(ctx):
-    from paper_2605_14103_amd import _lib, pf
+def test_direct_newton_on_the_2000_bus_grid(ctx):
+    """The 2000-bus grid's factor (36 k values per scenario) does not fit LDS
+    and lives in device memory: at its full batch of 1024 every scenario
+    converges, and spread scenarios agree with the oracle in V and in the
+    number of Newton updates (both take exact Newton steps)."""
+    from paper_2605_14103_amd import pf
     grid = tx.make_grid(tx.TX2000)
-    batch = tx.make_batch(grid, tx.TX2000, batch=2)
+    batch = tx.make_batch(grid, tx.TX2000)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    res = _solve(net, batch, nr_direct=1)
+    conv = res.converged.cpu().numpy()
+    nit = res.newton_iters.cpu().numpy()
+    say(f"tx2000 direct: converged {int(conv.sum())} of {batch.batch}, newton {np.bincount(nit).tolist()}, "
+        f"mismatch max {res.mismatch.cpu().numpy().max():.2e}")
+    assert conv.all() and res.mismatch.cpu().numpy().max() <= 1e-8
+    assert_high_voltage(res.v.cpu().numpy(), HV_FLOOR_TX, "tx2000 direct")
+    cols = spread_cols(batch.batch, 32)
+    V, it, ok, _ = onr.nr_solve_batch(grid, batch, columns=cols)
+    da, dm = angle_err(res.v.cpu().numpy()[cols], V)
+    say(f"tx2000 direct: max angle err {da:.2e}, max |V| err {dm:.2e}")
+    assert ok.all() and da <= TOL_A and dm <= TOL_V
+    np.testing.assert_array_equal(nit[cols], it)
+    # the GMRES path on the same network afterwards gives the same solutions
+    g = _solve(net, batch)
+    da, dm = angle_err(g.v.cpu().numpy(), res.v.cpu().numpy())
+    assert g.converged.cpu().numpy().all() and da <= 2 * TOL_A and dm <= 2 * TOL_V
+    net.close()
+
+
+def test_direct_newton_refuses_a_network_too_large(ctx):
+    """Above 2048 buses the LDS no longer holds V, I, the right-hand side and
+    x of one scenario: the direct step is refused, the network stays usable."""
+    from paper_2605_14103_amd import _lib, pf
+    cfg = tx.TxConfig("tx3000", n_bus=3000, n_pv=450, n_branch=3900, batch=2, seed=3000,
+                      perturbation="uniform", spread=0.2)
+    grid = tx.make_grid(cfg)
+    batch = tx.make_batch(grid, cfg, batch=2)
     net = pf.TxNetwork.from_grid(ctx, grid)
     with pytest.raises(_lib.PfError) as e:
         _solve(net, batch, nr_direct=1)
-    assert e.value.status == _lib.PF_INVALID_ARG and "factor values" in str(e.value)
+    assert e.value.status == _lib.PF_INVALID_ARG and "too large for the direct Newton step" in str(e.value)
     # the GMRES path still works on the same network afterwards
     res = _solve(net, batch)
     assert res.converged.cpu().numpy().all()

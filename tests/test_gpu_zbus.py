@@ -152,3 +152,34 @@ def test_sparse_variant(ctx, precision):
         say(f"{cfg.name} sparse vs dense {precision}: max |dv| {dv:.2e}")
         assert dv <= 2e-6
         net.close()
+
+
+@pytest.mark.parametrize("sparse", [0, 1])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_async_enqueue_equals_host_checked(ctx, precision, sparse):
+    """All iterations enqueued at once (device-side exits) against the
+    host-checked loop (the default): the same kernels on the same data, so every output
+    agrees bit for bit; a second call with a smaller batch on the same
+    network (its counts start from zero again) agrees too, and an iteration
+    cap below convergence stops both at the same iterate."""
+    import torch
+    from paper_2605_14103_amd import pf
+    cfg = fdm.FeederConfig("feeder120", n_bus=120, max_depth=25, batch=300, seed=121)
+    fd = fdm.make_feeder(cfg)
+    batch = fdm.make_batch(fd, cfg)
+    net = pf.DistNetwork.from_feeder(ctx, fd)
+    prec = pf.precision(precision)
+    for b, extra in ((300, {}), (37, {}), (300, {"zbus_max_iter": 3})):
+        sub = fdm.FeederBatch(batch.s_wye[:b], batch.s_delta[:b])
+        ra = _solve(net, sub, precision=prec, zbus_sparse=sparse, zbus_async=1, **extra)
+        rh = _solve(net, sub, precision=prec, zbus_sparse=sparse, zbus_async=0, **extra)
+        torch.cuda.synchronize()
+        for f in ("v", "iters", "converged", "mismatch", "sum_abs_change"):
+            assert torch.equal(getattr(ra, f), getattr(rh, f)), f"{f} differs (batch {b}, {extra})"
+        conv = ra.converged.cpu().numpy()
+        say(f"async feeder120 {precision} sparse={sparse} batch {b} {extra}: converged {int(conv.sum())}, "
+            f"iters max {int(ra.iters.max())}")
+        assert conv.all() if not extra else not conv.any()
+    _check(fd, batch, _solve(net, batch, precision=prec, zbus_sparse=sparse), spread_cols(300, 8),
+           f"feeder120 async {precision} sparse={sparse}")
+    net.close()
