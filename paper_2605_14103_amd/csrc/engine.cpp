@@ -106,13 +106,15 @@ uint64_t dist_slot_bytes(const DistNetwork& net, bool mixed) {
          + dist_row_bytes(net, mixed);     // one cohort's residual row
 }
 
-// Calls f(first, count) for each run of consecutive values of sorted `s`.
+// Calls f(first, count) for each run of consecutive values of sorted `s`,
+// all of which must lie in [0, limit).
 template <typename F>
-void for_runs(const std::vector<int>& s, F&& f) {
+void for_runs(const std::vector<int>& s, int limit, F&& f) {
   size_t i = 0;
   while (i < s.size()) {
     size_t j = i + 1;
     while (j < s.size() && s[j] == s[j - 1] + 1) ++j;
+    if (s[i] < 0 || s[j - 1] >= limit) fail(PF_INVALID_ARG, "slot outside the engine");
     f(s[i], (int)(j - i));
     i = j;
   }
@@ -284,7 +286,7 @@ Engine::~Engine() {
 void Engine::stage_in(Cohort& c, std::vector<int> slots, hipStream_t s) {
   if (slots.empty()) return;
   std::sort(slots.begin(), slots.end());
-  for_runs(slots, [&](int first, int cnt) {
+  for_runs(slots, max_slots, [&](int first, int cnt) {
     for (int i = 0; i < n_in; ++i)
       PFX_HIP(hipMemcpyAsync(in_d[i].as<double>() + (size_t)first * row, in_h[i] + (size_t)first * row,
                              sizeof(double) * (size_t)cnt * row, hipMemcpyHostToDevice, s));
@@ -388,7 +390,7 @@ void Engine::collect(Cohort& c, std::vector<int> slots, hipStream_t s) {
     a.slots = c.harv_d.as<int32_t>();
     zbus_finish_slots(net, a, s);
   }
-  for_runs(slots, [&](int first, int cnt) {
+  for_runs(slots, max_slots, [&](int first, int cnt) {
     PFX_HIP(hipMemcpyAsync(v_h + (size_t)first * vrow, v_d.as<double>() + (size_t)first * vrow,
                            sizeof(double) * (size_t)cnt * vrow, hipMemcpyDeviceToHost, s));
     PFX_HIP(hipMemcpyAsync(iters_h + first, iters_d.as<int32_t>() + first, 4 * (size_t)cnt,
@@ -494,11 +496,17 @@ void Engine::cohort_loop(int ci) {
       collect(c, done, c.stream);
     } catch (const std::exception& e) {
       // a failed step fails every request with a scenario in this cohort
+      // (admitted slots included, whether or not staging got to add them)
       err = e.what();
-      done.insert(done.end(), c.active.begin(), c.active.end());
+      (void)hipStreamSynchronize(c.stream);
+      std::vector<int> all(c.active);
+      all.insert(all.end(), admitted.begin(), admitted.end());
+      all.insert(all.end(), done.begin(), done.end());
+      std::sort(all.begin(), all.end());
+      all.erase(std::unique(all.begin(), all.end()), all.end());
+      done.swap(all);
       c.active.clear();
       c.fresh.clear();
-      (void)hipStreamSynchronize(c.stream);
     }
     {
       std::lock_guard<std::mutex> lk(mu);
