@@ -526,8 +526,10 @@ def bench_adjoint(steps: int, warmup: int) -> dict:
     return line
 
 
-def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1)) -> dict:
-    """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder)."""
+def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20, 1, 2), half: bool = True) -> dict:
+    """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder).
+
+    streams and step_iters are per engine (30-bus, 2000-bus, feeder)."""
     from paper_2605_14103_amd import pf, serve
     from workloads import feeder as fdm
     from workloads import serving as wsv
@@ -548,14 +550,17 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1)) -> dict:
         return b.s_wye, b.s_delta
 
     out = {}
-    half = wsv.make_trace(wsv.SERVING, n_requests=n_requests // 2, lam=lam / 2)
-    for prec, tr, key in (("fp64", trace, "fp64"), ("mixed", trace, "mixed"), ("fp64", half, "fp64_half_load")):
+    half_trace = wsv.make_trace(wsv.SERVING, n_requests=n_requests // 2, lam=lam / 2)
+    runs = [("fp64", trace, "fp64"), ("mixed", trace, "mixed")]
+    if half:
+        runs.append(("fp64", half_trace, "fp64_half_load"))
+    for prec, tr, key in runs:
         ctx = pf.Context(0)
         nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
                 pf.DistNetwork.from_feeder(ctx, fd)]
         budgets = (1 << 30, 24 << 30, 4 << 30)
-        engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec))
-                   for n, b, s in zip(nets, budgets, streams)]
+        engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec), step_iters=k)
+                   for n, b, s, k in zip(nets, budgets, streams, step_iters)]
         # warm-up: one small request per engine (code objects, first launches)
         warm = [r for r in wsv.make_trace(wsv.SERVING, n_requests=30, lam=lam) if r.n_scen <= 8][:6]
         serve.replay(engines, warm, inputs, speed=100.0)
@@ -579,9 +584,10 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1)) -> dict:
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
             "config": {"workload": f"serving mix: Poisson lambda={lam}/s, {n_requests} requests over tx30, "
-                                   f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8"},
+                                   f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8",
+                       "streams": list(streams), "step_iters": list(step_iters)},
             "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
-            "fp64": out["fp64"], "mixed": out["mixed"], "fp64_half_load": out["fp64_half_load"]}
+            "fp64": out["fp64"], "mixed": out["mixed"], "fp64_half_load": out.get("fp64_half_load")}
 
 
 def bench_sweep(steps: int, warmup: int) -> dict:
@@ -686,6 +692,9 @@ def main() -> int:
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
     ap.add_argument("--streams", default="1,2,1",
                     help="serving: HIP streams of the 30-bus, 2000-bus and feeder engines")
+    ap.add_argument("--step-iters", default="20,1,2",
+                    help="serving: Newton updates / fixed-point iterations per engine step, per engine")
+    ap.add_argument("--no-half", action="store_true", help="serving: skip the half-load replay")
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
@@ -716,7 +725,8 @@ def main() -> int:
     elif a.workload == "adjoint":
         line = bench_adjoint(a.steps, a.warmup)
     elif a.workload == "serving":
-        line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")))
+        line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")),
+                             tuple(int(x) for x in a.step_iters.split(",")), half=not a.no_half)
     elif a.workload == "sweep":
         line = bench_sweep(a.steps, a.warmup)
     elif a.workload == "feeder_sizes":
@@ -753,7 +763,8 @@ def all_configs(a) -> dict:
                     ("feeder300_b4096", lambda: bench_feeder(a.steps, a.warmup, a.sub_cpu.get("feeder"))),
                     ("adjoint_tx2000_b256", lambda: bench_adjoint(a.steps, a.warmup)),
                     ("serving_mix", lambda: bench_serving(a.requests, a.lam,
-                                                          tuple(int(x) for x in a.streams.split(","))))):
+                                                          tuple(int(x) for x in a.streams.split(",")),
+                                                          tuple(int(x) for x in a.step_iters.split(","))))):
         t = time.perf_counter()
         try:
             out[key] = _sub(fn())
