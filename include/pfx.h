@@ -96,6 +96,14 @@ typedef struct pf_opts {
   /* serving engine */
   int32_t step_iters;         /* Newton updates or fixed-point iterations per engine step of a
                                  request-driven engine, 1..1000, default 1 */
+  /* inexact Newton forcing term of the GMRES Newton step */
+  int32_t forcing;            /* 0: every Newton step's GMRES solve stops at gmres_rtol;
+                                 1 (default): adaptive (Eisenstat-Walker choice 2): eta_0 = forcing_max,
+                                 eta_k = 0.9 (|F_k| / |F_k-1|)^2, kept at least 0.9 eta_k-1^2
+                                 when that exceeds 0.1, at most forcing_max, and at least
+                                 gmres_rtol and 0.1 tol / |F_k| (no solve tighter than the
+                                 fixed tolerance or than reaching tol needs) */
+  double forcing_max;         /* largest adaptive forcing term, (0, 1), default 0.01 */
 } pf_opts;
 
 void pf_opts_default(pf_opts* out);

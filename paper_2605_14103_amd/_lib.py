@@ -36,6 +36,8 @@ class PfOpts(ctypes.Structure):
         ("zbus_async", c_int32),
         ("nr_direct", c_int32),
         ("step_iters", c_int32),
+        ("forcing", c_int32),
+        ("forcing_max", c_double),
     ]
 
 

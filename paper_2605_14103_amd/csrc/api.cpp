@@ -78,6 +78,8 @@ pf_opts resolve_opts(const pf_opts* o) {
   require(r.nr_direct == 0 || r.nr_direct == 1, "nr_direct must be 0 or 1");
   require(r.zbus_async == 0 || r.zbus_async == 1, "zbus_async must be 0 or 1");
   require(r.step_iters >= 1 && r.step_iters <= 1000, "step_iters must be 1..1000");
+  require(r.forcing == 0 || r.forcing == 1, "forcing must be 0 or 1");
+  require(r.forcing_max > 0 && r.forcing_max < 1, "forcing_max must be in (0, 1)");
   return r;
 }
 
@@ -127,6 +129,8 @@ void pf_opts_default(pf_opts* o) {
   o->nr_direct = 0;
   o->zbus_async = 0;
   o->step_iters = 1;
+  o->forcing = 1;
+  o->forcing_max = 0.01;
 }
 
 const char* pf_last_error(void) { return g_last_error.c_str(); }

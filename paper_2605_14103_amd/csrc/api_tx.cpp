@@ -159,6 +159,8 @@ void tx_solve(pf_tx_network* h, const pf_opts* opts, int32_t batch, int64_t ld, 
   a.tol = o.tol;
   a.diverge = o.diverge;
   a.rtol = o.gmres_rtol;
+  a.forcing = o.forcing;
+  a.forcing_max = o.forcing_max;
   a.max_newton = o.max_newton;
   a.restart = o.gmres_restart;
   a.max_restarts = o.gmres_max_restarts;

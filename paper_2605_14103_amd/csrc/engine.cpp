@@ -320,6 +320,8 @@ std::vector<int> Engine::step(Cohort& c, int iters, hipStream_t s) {
     a.tol = opts.tol;
     a.diverge = opts.diverge;
     a.rtol = opts.gmres_rtol;
+    a.forcing = opts.forcing;
+    a.forcing_max = opts.forcing_max;
     a.max_newton = opts.max_newton;
     a.restart = opts.gmres_restart;
     a.max_restarts = opts.gmres_max_restarts;

@@ -104,6 +104,8 @@ pf_status pf_tx_solve_noalloc(pf_tx_network* h, const pf_opts* opts, int32_t bat
     a.tol = o.tol;
     a.diverge = o.diverge;
     a.rtol = o.gmres_rtol;
+    a.forcing = o.forcing;
+    a.forcing_max = o.forcing_max;
     a.max_newton = o.max_newton;
     a.restart = o.gmres_restart;
     a.max_restarts = o.gmres_max_restarts;

@@ -859,11 +859,19 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
       }
     }
     __syncthreads();
+    // x += V y: the basis vector index outermost, so each vector's loads
+    // for all bus slots are in flight together
+    {
+      double acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      double acc = ws.ld(xpl, k);
-      for (int i = 0; i < steps; ++i) acc += (double)s.yv[i] * (double)basis.ld(i, k);
-      ws.st(xpl, k, acc);
+      for (int k = 0; k < K; ++k) acc[k] = ws.ld(xpl, k);
+      for (int i = 0; i < steps; ++i) {
+        const double yi = (double)s.yv[i];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += yi * (double)basis.ld(i, k);
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) ws.st(xpl, k, acc[k]);
     }
     done = !(res > rtol * beta0);
   }
@@ -934,6 +942,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   bool conv = false;
   double fnorm = 0.0;
   double work = 0.0;
+  double fprev = 0.0, eta = 0.0;   // the previous step's |F| and forcing term
   int par = 0;
   // A resumed scenario's workspace already holds the mismatch of its
   // iterate (tested before it was saved), so it goes straight to the solve.
@@ -943,6 +952,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     gtotal = sst->gtotal;
     fnorm = sst->fnorm;
     work = sst->work;
+    fprev = sst->fprev;
+    eta = sst->eta;
   }
   int steps = 0;
   for (;;) {
@@ -967,17 +978,41 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
           sst->gtotal = gtotal;
           sst->fnorm = fnorm;
           sst->work = work;
+          sst->fprev = fprev;
+          sst->eta = eta;
           a.step_done[blockIdx.x] = 0;
         }
         return;
       }
     }
     resume = false;
+    // Inexact Newton: the linear solve's relative tolerance.  Adaptive
+    // (Eisenstat and Walker's choice 2): loose while far from the solution,
+    // tightening with the square of the mismatch's decrease, but never
+    // tighter than the fixed tolerance rtol nor than reaching tol from the
+    // current mismatch requires.
+    double rt = a.rtol;
+    if (a.forcing) {
+      double e = a.forcing_max;
+      if (newton > 0) {
+        const double q = fnorm / fprev;
+        e = 0.9 * q * q;
+        const double safe = 0.9 * eta * eta;
+        if (safe > 0.1 && safe > e) e = safe;
+        if (e > a.forcing_max) e = a.forcing_max;
+      }
+      const double floor = 0.1 * a.tol / fnorm;
+      if (e < floor) e = floor;
+      if (e < a.rtol) e = a.rtol;
+      eta = e;
+      rt = e;
+    }
+    fprev = fnorm;
     // right-hand side -F in place (own rows)
 #pragma unroll
     for (int k = 0; k < K; ++k) ws.st(FP, k, -ws.ld(FP, k));
     bool lin_ok;
-    gtotal += gmres_solve<T, BLOCK, KB>(apply_j, apply_m, ws, FP, DXP, basis, R, a.max_restarts, (T)a.rtol, s,
+    gtotal += gmres_solve<T, BLOCK, KB>(apply_j, apply_m, ws, FP, DXP, basis, R, a.max_restarts, (T)rt, s,
                                         &lin_ok, bm, &work);
     // Newton update (eq. (3)), FP64, own buses
 #pragma unroll

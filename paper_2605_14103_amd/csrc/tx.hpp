@@ -140,7 +140,7 @@ void nr_shape(int n, int* block, int* kb);
 // tested), 2 = finished (outputs written).
 struct NrSlotState {
   int32_t phase, newton, gtotal, pad;
-  double fnorm, work;
+  double fnorm, work, fprev, eta;
 };
 
 // Launchers (nr_kernels.hip).
@@ -158,6 +158,9 @@ struct NRLaunch {
   double* work_bytes;
   double tol, diverge, rtol;
   int max_newton, restart, max_restarts;
+  // adaptive forcing term (1) or rtol for every Newton step (0); see pf_opts
+  int forcing;
+  double forcing_max;
   double* ws_d;
   int64_t ws_d_stride;
   void* ws_basis;

@@ -43,7 +43,7 @@ def test_defaults_and_option_struct():
     assert o.precision == _lib.PF_FP64 and o.tol == 1e-8 and o.max_newton == 20
     assert o.gmres_restart == 30 and o.zbus_max_iter == 100 and o.precond_block == 0
     assert o.zbus_sparse == 0 and o.nr_direct == 0 and o.gmres_rtol == 0.0  # 0 selects the default 1e-3
-    assert o.step_iters == 1
+    assert o.step_iters == 1 and o.zbus_async == 0 and o.forcing == 1 and o.forcing_max == 0.01
     with pytest.raises(TypeError):
         _lib.opts(not_an_option=1)
 
