@@ -526,7 +526,8 @@ def bench_adjoint(steps: int, warmup: int) -> dict:
     return line
 
 
-def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20, 1, 2), half: bool = True) -> dict:
+def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20, 1, 2), half: bool = True,
+                  forcing: int = 0) -> dict:
     """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder).
 
     streams and step_iters are per engine (30-bus, 2000-bus, feeder)."""
@@ -559,7 +560,8 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20
         nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
                 pf.DistNetwork.from_feeder(ctx, fd)]
         budgets = (1 << 30, 24 << 30, 4 << 30)
-        engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec), step_iters=k)
+        engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec), step_iters=k,
+                             forcing=forcing)
                    for n, b, s, k in zip(nets, budgets, streams, step_iters)]
         # warm-up: one small request per engine (code objects, first launches)
         warm = [r for r in wsv.make_trace(wsv.SERVING, n_requests=30, lam=lam) if r.n_scen <= 8][:6]
@@ -585,7 +587,7 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20
             "data": "synthetic",
             "config": {"workload": f"serving mix: Poisson lambda={lam}/s, {n_requests} requests over tx30, "
                                    f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8",
-                       "streams": list(streams), "step_iters": list(step_iters)},
+                       "streams": list(streams), "step_iters": list(step_iters), "forcing": forcing},
             "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
             "fp64": out["fp64"], "mixed": out["mixed"], "fp64_half_load": out.get("fp64_half_load")}
 
@@ -695,6 +697,8 @@ def main() -> int:
     ap.add_argument("--step-iters", default="20,1,2",
                     help="serving: Newton updates / fixed-point iterations per engine step, per engine")
     ap.add_argument("--no-half", action="store_true", help="serving: skip the half-load replay")
+    ap.add_argument("--forcing", type=int, default=0,
+                    help="serving engines: fixed (0, lower tail latency) or adaptive (1) forcing term")
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
@@ -726,7 +730,7 @@ def main() -> int:
         line = bench_adjoint(a.steps, a.warmup)
     elif a.workload == "serving":
         line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")),
-                             tuple(int(x) for x in a.step_iters.split(",")), half=not a.no_half)
+                             tuple(int(x) for x in a.step_iters.split(",")), half=not a.no_half, forcing=a.forcing)
     elif a.workload == "sweep":
         line = bench_sweep(a.steps, a.warmup)
     elif a.workload == "feeder_sizes":
@@ -764,7 +768,8 @@ def all_configs(a) -> dict:
                     ("adjoint_tx2000_b256", lambda: bench_adjoint(a.steps, a.warmup)),
                     ("serving_mix", lambda: bench_serving(a.requests, a.lam,
                                                           tuple(int(x) for x in a.streams.split(",")),
-                                                          tuple(int(x) for x in a.step_iters.split(","))))):
+                                                          tuple(int(x) for x in a.step_iters.split(",")),
+                                                          forcing=a.forcing))):
         t = time.perf_counter()
         try:
             out[key] = _sub(fn())

@@ -102,7 +102,11 @@ typedef struct pf_opts {
                                  eta_k = 0.9 (|F_k| / |F_k-1|)^2, kept at least 0.9 eta_k-1^2
                                  when that exceeds 0.1, at most forcing_max, and at least
                                  gmres_rtol and 0.1 tol / |F_k| (no solve tighter than the
-                                 fixed tolerance or than reaching tol needs) */
+                                 fixed tolerance or than reaching tol needs).  The adaptive term
+                                 saves GMRES steps (about 5 % of a 2000-bus batch solve) but
+                                 gives some scenarios one more Newton update, which in the
+                                 step-level serving engine lengthens the requests that hold
+                                 them: serving engines meant for low tail latency should use 0 */
   double forcing_max;         /* largest adaptive forcing term, (0, 1), default 0.01 */
 } pf_opts;
 

@@ -2,9 +2,9 @@
 
 The admission, slot assignment, continuous batching and stream overlap all
 happen inside the native engines (``pf.Engine``); this module only plays a
-request trace against them in real time from one host thread: it submits
-each request when its arrival time comes, harvests finished requests while
-it waits, and records per-request latency and throughput.
+request trace against them in real time: one host thread submits each
+request when its arrival time comes, another harvests finished requests,
+and per-request latency and throughput are recorded.
 
 An engine here is anything with ``submit(rid, *inputs)``, ``poll(max_ids,
 timeout) -> [rid]`` and ``fetch(rid)`` returning an object with ``converged``,
@@ -13,6 +13,7 @@ engine's own clock) fields, plus ``info()``.
 """
 from __future__ import annotations
 
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -82,7 +83,10 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
 
     ``inputs(req)`` returns the request's input arrays (host).  ``speed`` > 1
     compresses the arrival times.  Requests still unfinished ``timeout_s``
-    after the last arrival are reported as failed.
+    after the last arrival are reported as failed.  One thread submits each
+    request when its arrival time comes; a second thread harvests finished
+    requests (poll, fetch, accounting), so fetching large results never
+    delays a submission.
     """
     order = sorted(trace, key=lambda r: r.t_arrive)
     pending: dict[tuple[int, int], tuple] = {}
@@ -90,17 +94,22 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
     if not order:
         return stats
     staged = [(r, inputs(r)) for r in order]
+    lock = threading.Lock()
+    submitted_all = threading.Event()
+    t0 = time.perf_counter()
 
-    def harvest(wait: float) -> None:
+    def harvest_once(wait: float) -> bool:
         got = False
         for k, eng in enumerate(engines):
             for rid in eng.poll(256, wait if not got and k == 0 else 0.0):
                 got = True
-                req, t_sub_host = pending.pop((k, rid))
+                with lock:
+                    req, t_sub_host = pending.pop((k, rid))
                 try:
                     res = eng.fetch(rid)
                 except Exception as e:   # a failed launch fails only its own requests
-                    stats.failed.append((rid, str(e)))
+                    with lock:
+                        stats.failed.append((rid, str(e)))
                     continue
                 ok = res.converged.astype(bool) & (res.mismatch <= tol)
                 sub, launch, done = (float(x) for x in res.times)
@@ -109,28 +118,44 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
                            service=done - launch, n_converged=int(ok.sum()),
                            max_mismatch=float(res.mismatch[ok].max()) if ok.any() else float("nan"))
                 s.t_done = req.t_arrive / speed + s.latency
-                stats.served.append(s)
+                with lock:
+                    stats.served.append(s)
+        return got
 
-    t0 = time.perf_counter()
-    for req, arrays in staged:
+    def harvester() -> None:
+        deadline = None
         while True:
-            now = time.perf_counter() - t0
-            ahead = req.t_arrive / speed - now
-            if ahead <= 0:
-                break
-            harvest(min(ahead, 0.002))
+            with lock:
+                left = len(pending)
+            if submitted_all.is_set():
+                if left == 0:
+                    return
+                if deadline is None:
+                    deadline = time.perf_counter() + timeout_s
+                elif time.perf_counter() > deadline:
+                    return
+            harvest_once(0.001)
+
+    th = threading.Thread(target=harvester, daemon=True)
+    th.start()
+    for req, arrays in staged:
+        ahead = req.t_arrive / speed - (time.perf_counter() - t0)
+        if ahead > 0:
+            time.sleep(ahead)   # releases the interpreter lock to the harvester
         eng = engines[req.network]
-        pending[(req.network, req.rid)] = (req, time.perf_counter() - t0)
+        with lock:
+            pending[(req.network, req.rid)] = (req, time.perf_counter() - t0)
         try:
             eng.submit(req.rid, *arrays)
         except Exception as e:     # e.g. a request larger than the engine's slots
-            pending.pop((req.network, req.rid))
-            stats.failed.append((req.rid, str(e)))
-    deadline = time.perf_counter() + timeout_s
-    while pending and time.perf_counter() < deadline:
-        harvest(0.005)
-    for (k, rid), _ in pending.items():
-        stats.failed.append((rid, "not finished before the time-out"))
+            with lock:
+                pending.pop((req.network, req.rid))
+                stats.failed.append((req.rid, str(e)))
+    submitted_all.set()
+    th.join()
+    with lock:
+        for (k, rid), _ in pending.items():
+            stats.failed.append((rid, "not finished before the time-out"))
     t_first = order[0].t_arrive / speed
     stats.duration = max((s.t_done for s in stats.served), default=t_first) - t_first
     stats.offered_span = (order[-1].t_arrive - order[0].t_arrive) / speed
