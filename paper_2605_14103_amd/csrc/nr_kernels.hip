@@ -370,6 +370,59 @@ __device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (
   }
 }
 
+// One group of four entries of a packed sliced layout (group index g) into
+// v[0..3] and c[0..3].
+template <typename T>
+__device__ __forceinline__ void pgroup(const PSell<T>& a, unsigned g, T* v, int* c) {
+  const int2 cc = cld(reinterpret_cast<const int2*>(a.col), g);
+  c[0] = cc.x & 0xffff;
+  c[1] = (int)((unsigned)cc.x >> 16);
+  c[2] = cc.y & 0xffff;
+  c[3] = (int)((unsigned)cc.y >> 16);
+  if constexpr (sizeof(T) == 8) {
+    const int4 p = cld(reinterpret_cast<const int4*>(a.val), 2 * g);
+    const int4 q = cld(reinterpret_cast<const int4*>(a.val), 2 * g + 1);
+    __builtin_memcpy(&v[0], &p, 16);
+    __builtin_memcpy(&v[2], &q, 16);
+  } else {
+    const int4 p = cld(reinterpret_cast<const int4*>(a.val), g);
+    __builtin_memcpy(v, &p, 16);
+  }
+}
+
+// dst[r] = sum over row r of val * x[col] for the rows of a by-length packed
+// layout (rid gives each lane's row, -1 for padding); rows in rounds of two
+// groups (eight entries), then one group.
+template <int KB, int NW, typename T>
+__device__ __forceinline__ void sell_slots_store(const PSell<T>& a, const int* rid, const T* x, T* dst) {
+  const int wv = wave_id(), lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const unsigned sl = (unsigned)(k * NW + wv);
+    const int o = cld(a.off, sl);
+    const int wd = cld(a.width, sl);
+    const int r = cld(rid, sl * WAVE + lane);
+    T acc = 0;
+    int p = 0;
+    for (; p + 2 <= wd; p += 2) {
+      T v[8];
+      int c[8];
+      pgroup(a, (unsigned)(o + p * WAVE + lane), v, c);
+      pgroup(a, (unsigned)(o + (p + 1) * WAVE + lane), v + 4, c + 4);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u] * x[c[u]];
+    }
+    if (p < wd) {
+      T v[4];
+      int c[4];
+      pgroup(a, (unsigned)(o + p * WAVE + lane), v, c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += v[u] * x[c[u]];
+    }
+    if (r >= 0) dst[r] = acc;
+  }
+}
+
 // out[OFF + k] = (A^-1 x)_i for the bus slots i = t + k BLOCK (zero past N), by
 // the explicit factor passes E1 (rows into `aux` / the core right-hand side
 // into `tmp`), E2 (dense core into aux past c), E3 (rows in matrix order, read
@@ -378,8 +431,11 @@ __device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (
 // barriers (one when the core is empty); the caller places one before aux or
 // tmp is written again.  A factor applied directly (f.direct) reads x
 // throughout and has no barrier: the caller places one before x is written.
-template <typename T, int BLOCK, int KB, int OFF, int K>
-__device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K]) {
+// With TO_LDS (not for a direct factor) E3 takes the by-length layout and
+// stores x_i to dst[i] (i < N) instead of filling out; dst may be x itself,
+// since x is no longer read by then.
+template <typename T, int BLOCK, int KB, int OFF, int K, bool TO_LDS = false>
+__device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&out)[K], T* dst = nullptr) {
   constexpr int NW = BLOCK / WAVE;
   if (f.direct) {  // one sliced pass over A^-1 itself; no barrier, x read throughout
     T acc[KB];
@@ -462,6 +518,10 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
     aux[f.c + i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   }
   if (f.k > 0) __syncthreads();  // with no core, E3 reads only what E1 wrote
+  if constexpr (TO_LDS) {
+    sell_slots_store<KB, NW>(f.e3s, f.e3s_row, aux, dst);
+    return;
+  }
   T acc[KB];
   sell_slots_dot<KB, NW>(f.e3, aux, acc);
 #pragma unroll
@@ -473,9 +533,10 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
 //   z_Theta = (B' + eps I)^-1 diag(|V_Theta|)^-1 w_Theta
 //   z_Q     = (B'' + eps I)^-1 diag(|V_Q|)^-1 (w_Q - G z_Theta)
 // LDS use: the B' right-hand side at [0, nth) with its passes at [nth, 2 nth);
-// z_Theta at [0, nth); the B'' right-hand side at [nth, nth + npq) with its
-// passes at [0, npq).  The caller guarantees that no thread still reads the
-// LDS vector area.
+// z_Theta at [0, nth) (the B' factor's E3 pass stores it there directly,
+// and each thread reads its own entries back); the B'' right-hand side at
+// [nth, nth + npq) with its passes at [0, npq).  The caller guarantees that
+// no thread still reads the LDS vector area.
 template <typename T, int BLOCK, int KB>
 __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB], const Smem<T>& s) {
   constexpr int NW = BLOCK / WAVE;
@@ -490,18 +551,32 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
     if (i < nth) X[i] = v;
   }
   __syncthreads();
-  efac_apply<T, BLOCK, KB, 0>(net.bp, X, Y, s.tmp, w);
-  if (npq > 0) {
-    // X was last read before the first barrier of the B' passes (unless B' is
-    // applied directly), so z_Theta may overwrite it at once; the barrier
-    // below also orders the B' passes' reads of Y before Y is written again.
-    if (net.bp.direct) __syncthreads();
+  if (net.bp.direct) {
+    efac_apply<T, BLOCK, KB, 0>(net.bp, X, Y, s.tmp, w);
+    if (npq > 0) {
+      // the direct pass read X throughout; the barrier after the stores also
+      // orders its reads of Y before Y is written again
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const unsigned i = row<BLOCK>(k);
+        if (i < nth) X[i] = w[k];
+      }
+      __syncthreads();
+    }
+  } else {
+    // X was last read before the first barrier of the B' passes, so their
+    // E3 pass stores z_Theta over it; the barrier also orders the passes'
+    // reads of Y before Y is written again.
+    efac_apply<T, BLOCK, KB, 0, 2 * KB, true>(net.bp, X, Y, s.tmp, w, X);
+    __syncthreads();
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);
-      if (i < nth) X[i] = w[k];
+      w[k] = i < nth ? X[i] : (T)0;
     }
-    __syncthreads();
+  }
+  if (npq > 0) {
     const TxDev<T> nt = load_desc(netp);
     T gz[KB];
     sell_slots_dot<KB, NW>(nt.g, X, gz);

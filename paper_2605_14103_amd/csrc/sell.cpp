@@ -67,6 +67,50 @@ void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b) {
   }
 }
 
+void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& b) {
+  const int ns = (int)rows.size() / SLICE;
+  std::vector<int> off(ns), width(ns);
+  int cur = 0;
+  for (int s = 0; s < ns; ++s) {
+    int w = 1;
+    for (int l = 0; l < SLICE; ++l) w = std::max(w, (int)rows[s * SLICE + l].size());
+    off[s] = cur;
+    width[s] = (w + 3) / 4;
+    cur += SLICE * width[s];
+  }
+  std::vector<unsigned short> col((size_t)4 * cur, 0);
+  std::vector<double> val((size_t)4 * cur, 0.0);
+  long entries = 0;
+  for (int s = 0; s < ns; ++s)
+    for (int l = 0; l < SLICE; ++l) {
+      const SellRow& r = rows[s * SLICE + l];
+      for (size_t p = 0; p < r.size(); ++p) {
+        const int c = std::get<0>(r[p]);
+        if (c < 0 || c > 65535) fail(PF_INVALID_ARG, "packed layout needs columns below 65536");
+        const size_t q = 4 * ((size_t)off[s] + (p / 4) * SLICE + l) + p % 4;
+        col[q] = (unsigned short)c;
+        val[q] = std::get<1>(r[p]);
+      }
+      entries += (long)r.size();
+    }
+  b.n_slices = ns;
+  b.entries = entries;
+  b.off = upload(ctx, off);
+  b.width = upload(ctx, width);
+  b.col = upload(ctx, col);
+  b.val64 = upload(ctx, val);
+  b.val32 = upload(ctx, std::vector<float>(val.begin(), val.end()));
+}
+
+template <>
+PSell<double> PSellBuffers::view<double>() const {
+  return PSell<double>{off.as<int>(), width.as<int>(), col.as<unsigned short>(), val64.as<double>()};
+}
+template <>
+PSell<float> PSellBuffers::view<float>() const {
+  return PSell<float>{off.as<int>(), width.as<int>(), col.as<unsigned short>(), val32.as<float>()};
+}
+
 template <>
 Sell<double> SellBuffers::view<double>() const {
   return Sell<double>{off.as<int>(), width.as<int>(), col.as<int>(), val64.as<double>()};

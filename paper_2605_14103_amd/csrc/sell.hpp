@@ -22,6 +22,20 @@ struct Sell {
   const V* val;
 };
 
+// Packed sliced layout for real values: the slices of Sell, but each lane's
+// entries are grouped in fours.  Group g of the row on lane l of slice s is
+// group index off[s] + 64 g + l; it holds four values (val[4 index ..]) and
+// four 16-bit columns (col[4 index ..]), so a group is one 8-byte column load
+// and one (FP32) or two (FP64) 16-byte value loads.  Offsets and widths count
+// groups; padding entries have column 0 and value 0.
+template <typename V>
+struct PSell {
+  const int* off;
+  const int* width;
+  const unsigned short* col;
+  const V* val;
+};
+
 template <typename T>
 struct Vec2;
 template <>
@@ -58,5 +72,16 @@ SellHost build_sell(const std::vector<SellRow>& rows, int quantum = 1);
 
 // Device copies: values in FP64 and FP32, complex values as (re, im) pairs.
 void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b);
+
+// Packed layout (real values, columns below 65536) with device copies of its
+// values in FP64 and FP32; rows as for build_sell (a multiple of 64).
+struct PSellBuffers {
+  int n_slices = 0;
+  long entries = 0;
+  DeviceBuffer off, width, col, val64, val32;
+  template <typename V>
+  PSell<V> view() const;
+};
+void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& b);
 
 }  // namespace pfx

@@ -37,6 +37,11 @@ struct EfDev {
   const int* e1_row;     // [n_slices * 64]
   const int* e1_wave;    // [n_waves * kb][4]: entry offset, width, first row id index, 0
   Sell<T> e3;
+  // The same E3 rows sorted by length into slices dealt to (slot, wave)
+  // positions k NW + w with balanced rounds; e3s_row[slice * 64 + lane] is
+  // the row's matrix row (-1 for padding).  Used where the result goes to LDS.
+  PSell<T> e3s;
+  const int* e3s_row;
   const T* sinv;         // S^-1 (k x k) in packs [l / P][i][P], P = 16 / sizeof(T)
   // With no dense core the inverse itself may be sparse enough to apply in one
   // pass: then `direct` is 1 and `inv` holds A^-1 by rows in bus order, with
@@ -86,7 +91,8 @@ struct EfBuffers {
   bool direct = false;
   SellBuffers inv;
   SellBuffers e1, e3;
-  DeviceBuffer e1_row, e1_wave, sinv64, sinv32;
+  PSellBuffers e3s;
+  DeviceBuffer e1_row, e1_wave, e3s_row, sinv64, sinv32;
   template <typename T>
   EfDev<T> view() const;
 };

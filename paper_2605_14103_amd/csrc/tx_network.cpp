@@ -66,6 +66,36 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
   SellHost h3 = build_sell(rows3, 4);
   upload_sell(ctx, h1, false, f.e1);
   upload_sell(ctx, h3, false, f.e3);
+  {
+    // E3 again with its rows sorted by length (the pass that stores its
+    // results to LDS rather than to the owning threads' registers): slices of
+    // 64 rows, longest first, each to the wave with the fewest rounds so far
+    // and a free slot; the slice goes to position slot * nw + wave.
+    std::vector<int> ord(N);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+      return E.e3[E.pinv[a]].size() > E.e3[E.pinv[b]].size();
+    });
+    const int ns = (N + SLICE - 1) / SLICE;
+    if (ns > nw * kb) fail(PF_INVALID_ARG, "factor does not fit the workgroup layout");
+    std::vector<Row> rows3s((size_t)nw * kb * SLICE);
+    std::vector<int> rid3((size_t)nw * kb * SLICE, -1), load3(nw, 0), cnt3(nw, 0);
+    for (int s = 0; s < ns; ++s) {
+      const int w4 = std::max(4, ((int)E.e3[E.pinv[ord[(size_t)s * SLICE]]].size() + 3) / 4 * 4);
+      int best = -1;
+      for (int w = 0; w < nw; ++w)
+        if (cnt3[w] < kb && (best < 0 || load3[w] < load3[best])) best = w;
+      const int pos = cnt3[best]++ * nw + best;
+      load3[best] += (w4 + 7) / 8;   // rounds of eight entries, then one of four
+      for (int l = 0; l < SLICE && s * SLICE + l < N; ++l) {
+        const int i = ord[(size_t)s * SLICE + l];
+        for (auto [p, v] : E.e3[E.pinv[i]]) rows3s[(size_t)pos * SLICE + l].push_back({p, v, 0.0});
+        rid3[(size_t)pos * SLICE + l] = i;
+      }
+    }
+    upload_psell(ctx, rows3s, f.e3s);
+    f.e3s_row = upload(ctx, rid3);
+  }
   // With no core, A^-1 = E3 E1 (times the permutation) may stay sparse: if its
   // sliced rows are not much longer than E1's and E3's together, it is
   // applied in one pass with no barrier inside.
@@ -175,6 +205,8 @@ EfDev<T> EfBuffers::view() const {
   d.e1_row = e1_row.as<int>();
   d.e1_wave = e1_wave.as<int>();
   d.e3 = e3.view<T>();
+  d.e3s = e3s.view<T>();
+  d.e3s_row = e3s_row.as<int>();
   d.sinv = f64 ? sinv64.as<T>() : sinv32.as<T>();
   d.direct = direct ? 1 : 0;
   d.inv = direct ? inv.view<T>() : Sell<T>{nullptr, nullptr, nullptr, nullptr};
