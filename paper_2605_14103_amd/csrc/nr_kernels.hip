@@ -171,19 +171,66 @@ __device__ __forceinline__ void bst(const Buf& b, float x, unsigned voff, unsign
 }
 
 // One scenario's FP64 workspace: 13 planes of NBP = KB BLOCK doubles.  Plane
-// F and DX span two planes each (angle plane, then magnitude plane).
+// F and DX span two planes each (angle plane, then magnitude plane).  With an
+// even slot count a thread's slots 2j and 2j + 1 of a plane are adjacent
+// (slot k of thread t at (k / G) G BLOCK + G t + k % G, G = 2), so that the
+// pair is read or written with one 16-byte access.
 enum WsPlane { TH = 0, VM, IVM, VRE, VIM, IRE, IIM, PIN, QIN, FP = 9, DXP = 11, WS_PLANES = 13 };
 
 template <int BLOCK, int KB>
 struct Ws {
   static constexpr unsigned NBP = (unsigned)KB * BLOCK;
+  static constexpr int G = KB % 2 == 0 ? 2 : 1;
   Buf b;
-  // plane a, bus slot k (k < 2 KB for the two-plane vectors F and DX)
-  __device__ __forceinline__ double ld(int a, int k) const {
-    return bld<double, WS_POLICY>(b, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
+  static __device__ __forceinline__ unsigned vo() { return threadIdx.x * (8u * G); }
+  static __device__ __forceinline__ unsigned so(int a, int k) {
+    return (unsigned)(a * (int)NBP + (k / G) * (G * BLOCK) + k % G) * 8u;
   }
-  __device__ __forceinline__ void st(int a, int k, double v) const {
-    bst<WS_POLICY>(b, v, threadIdx.x * 8u, (unsigned)(a * NBP + k * BLOCK) * 8u);
+  // plane a, bus slot k (k < 2 KB for the two-plane vectors F and DX)
+  __device__ __forceinline__ double ld(int a, int k) const { return bld<double, WS_POLICY>(b, vo(), so(a, k)); }
+  __device__ __forceinline__ void st(int a, int k, double v) const { bst<WS_POLICY>(b, v, vo(), so(a, k)); }
+  // x[k] = slot k of plane a for k < N (N = KB, or 2 KB for F and DX), in pairs
+  template <int N, typename T>
+  __device__ __forceinline__ void ld_all(int a, T (&x)[N]) const {
+#pragma unroll
+    for (int k = 0; k < N; k += G) {
+      if constexpr (G == 2) {
+        double d0, d1;
+        ld2(a, k, d0, d1);
+        x[k] = (T)d0;
+        x[k + 1] = (T)d1;
+      } else {
+        x[k] = (T)ld(a, k);
+      }
+    }
+  }
+  template <int N>
+  __device__ __forceinline__ void st_all(int a, const double (&x)[N]) const {
+#pragma unroll
+    for (int k = 0; k < N; k += G) {
+      if constexpr (G == 2) st2(a, k, x[k], x[k + 1]);
+      else st(a, k, x[k]);
+    }
+  }
+  // slots k and k + 1 (k even)
+  __device__ __forceinline__ void ld2(int a, int k, double& x0, double& x1) const {
+    if constexpr (G == 2) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)vo(), (int)so(a, k), WS_POLICY);
+      double d[2];
+      __builtin_memcpy(d, &v, 16);
+      x0 = d[0];
+      x1 = d[1];
+    } else {
+      x0 = ld(a, k);
+      x1 = ld(a, k + 1);
+    }
+  }
+  // Stores stay 8 bytes wide: with 16-byte stores here (whose data registers
+  // the next loads reuse at once) some scenarios of batches above one
+  // workgroup per CU read back wrong values, run to run differently.
+  __device__ __forceinline__ void st2(int a, int k, double x0, double x1) const {
+    st(a, k, x0);
+    st(a, k + 1, x1);
   }
   // The mismatch's V, I and 1/|V| as the inner solve reads them: FP64 planes,
   // or for an FP32 inner solve FP32 copies in the same planes (V and I as
@@ -193,7 +240,7 @@ struct Ws {
   __device__ __forceinline__ void put_vi(int k, double vr, double vi, double ivm) const {
     if constexpr (sizeof(T) == 4) {
       st(VRE, k, pack2(vr, vi));
-      bst<WS_POLICY>(b, (float)ivm, threadIdx.x * 8u, (unsigned)(IVM * NBP + k * BLOCK) * 8u);
+      bst<WS_POLICY>(b, (float)ivm, vo(), so(IVM, k));
     } else {
       st(VRE, k, vr);
       st(VIM, k, vi);
@@ -230,9 +277,49 @@ struct Ws {
   template <typename T>
   __device__ __forceinline__ T get_ivm(int k) const {
     if constexpr (sizeof(T) == 4) {
-      return bld<float, WS_POLICY>(b, threadIdx.x * 8u, (unsigned)(IVM * NBP + k * BLOCK) * 8u);
+      return bld<float, WS_POLICY>(b, vo(), so(IVM, k));
     } else {
       return ld(IVM, k);
+    }
+  }
+  // The same for the slot pair k, k + 1 (k even)
+  template <typename T>
+  __device__ __forceinline__ void get_v2(int k, T (&re)[2], T (&im)[2]) const {
+    if constexpr (sizeof(T) == 4) {
+      double d0, d1;
+      ld2(VRE, k, d0, d1);
+      unpack2(d0, re[0], im[0]);
+      unpack2(d1, re[1], im[1]);
+    } else {
+      ld2(VRE, k, re[0], re[1]);
+      ld2(VIM, k, im[0], im[1]);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void get_i2(int k, T (&re)[2], T (&im)[2]) const {
+    if constexpr (sizeof(T) == 4) {
+      double d0, d1;
+      ld2(IRE, k, d0, d1);
+      unpack2(d0, re[0], im[0]);
+      unpack2(d1, re[1], im[1]);
+    } else {
+      ld2(IRE, k, re[0], re[1]);
+      ld2(IIM, k, im[0], im[1]);
+    }
+  }
+  template <typename T>
+  __device__ __forceinline__ void get_ivm2(int k, T (&iv)[2]) const {
+    double d0, d1;
+    ld2(IVM, k, d0, d1);
+    if constexpr (sizeof(T) == 4) {
+      float f0[2], f1[2];
+      __builtin_memcpy(f0, &d0, 8);
+      __builtin_memcpy(f1, &d1, 8);
+      iv[0] = f0[0];
+      iv[1] = f1[0];
+    } else {
+      iv[0] = d0;
+      iv[1] = d1;
     }
   }
 
@@ -252,141 +339,88 @@ struct Ws {
   }
 };
 
-// The Krylov basis of one scenario: vectors of MP = 2 NBP entries of T.
+// The Krylov basis of one scenario: vectors of MP = 2 NBP entries of T.  A
+// thread's slots are stored in runs of G consecutive entries (G slots of 16
+// bytes in all where the slot count allows), so that the compiler reads and
+// writes a run with one wide access: slot k of thread t sits at
+// (k / G) G BLOCK + G t + k % G.
 template <typename T, int BLOCK, int KB>
 struct Basis {
   static constexpr unsigned MP = 2u * KB * BLOCK;
+  static constexpr int G = (16 / (int)sizeof(T) <= 2 * KB && (2 * KB) % (16 / (int)sizeof(T)) == 0)
+                               ? 16 / (int)sizeof(T) : 2;
   Buf b;
-  __device__ __forceinline__ T ld(int i, int k) const {
-    return bld<T, BASIS_POLICY>(b, threadIdx.x * (unsigned)sizeof(T),
-                                ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+  static __device__ __forceinline__ unsigned off(int i, int k) {
+    return ((unsigned)i * MP + (unsigned)(k / G) * (G * BLOCK) + (unsigned)(k % G)) * (unsigned)sizeof(T);
   }
-  __device__ __forceinline__ void st(int i, int k, T v) const {
-    bst<BASIS_POLICY>(b, v, threadIdx.x * (unsigned)sizeof(T),
-                      ((unsigned)i * MP + (unsigned)k * BLOCK) * (unsigned)sizeof(T));
+  // run g (slots g G .. g G + G - 1) of vector i: one load or store of G sizeof(T) bytes
+  __device__ __forceinline__ void ldg(int i, int g, T* e) const {
+    const unsigned vo = threadIdx.x * (unsigned)(G * sizeof(T)), so = off(i, g * G);
+    if constexpr (G * sizeof(T) == 16) {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)vo, (int)so, BASIS_POLICY);
+      __builtin_memcpy(e, &v, 16);
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)vo, (int)so, BASIS_POLICY);
+      __builtin_memcpy(e, &v, 8);
+    }
+  }
+  __device__ __forceinline__ void stg(int i, int g, const T* e) const {
+    const unsigned vo = threadIdx.x * (unsigned)(G * sizeof(T)), so = off(i, g * G);
+    if constexpr (G * sizeof(T) == 16) {
+      decltype(__builtin_amdgcn_raw_buffer_load_b128(b.r, 0, 0, 0)) v;
+      __builtin_memcpy(&v, e, 16);
+      __builtin_amdgcn_raw_buffer_store_b128(v, b.r, (int)vo, (int)so, BASIS_POLICY);
+    } else {
+      decltype(__builtin_amdgcn_raw_buffer_load_b64(b.r, 0, 0, 0)) v;
+      __builtin_memcpy(&v, e, 8);
+      __builtin_amdgcn_raw_buffer_store_b64(v, b.r, (int)vo, (int)so, BASIS_POLICY);
+    }
   }
 };
 
-// Rows by bus slot: the thread's bus slots k < KB are rows of slices
-// k NW + wave.  Slices are padded to widths that are multiples of 4 (with zero
-// entries), so each row is read in rounds of 4 independent entries with no
-// remainder loop.  body(k, val, col) accumulates one entry of slot k; after a
-// slot's row, done(k) runs and its results are pinned so that later slots do
-// not keep this slot's operands alive.
-// One row (slice s, this lane) in rounds of four entries.
-template <typename V, typename Body>
-__device__ __forceinline__ void sell_row4(const Sell<V>& a, int s, Body&& body) {
-  const int lane = lane_id();
-  const int o = cld(a.off, (unsigned)s);
-  const int wd = cld(a.width, (unsigned)s);
-  for (int p = 0; p < wd; p += 4) {
-    V v[4];
-    int c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
-      v[u] = cld(a.val, q);
-      c[u] = cld(a.col, q);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) body(v[u], c[u]);
-  }
-}
-
-template <int KB, int NW, typename V, typename Body, typename Done>
-__device__ __forceinline__ void sell_slots(const Sell<V>& a, Body&& body, Done&& done) {
-  const int wv = wave_id(), lane = lane_id();
-#pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    const int o = cld(a.off, (unsigned)(k * NW + wv));
-    const int wd = cld(a.width, (unsigned)(k * NW + wv));
-    for (int p = 0; p < wd; p += 4) {
-      V v[4];
-      int c[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const unsigned q = (unsigned)(o + (p + u) * WAVE + lane);
-        v[u] = cld(a.val, q);
-        c[u] = cld(a.col, q);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) body(k, v[u], c[u]);
-    }
-    done(k);
-  }
-}
-
-// acc[k] = sum over slot k's row of val * x[col], real values.  In FP32,
-// slots are taken in pairs whose rows advance together, so each round has
-// the loads of two rows in flight (in FP64 the extra registers cost more
-// than the overlap gains).
-template <int KB, int NW, typename T>
-__device__ __forceinline__ void sell_slots_dot(const Sell<T>& a, const T* x, T (&acc)[KB]) {
-  const int wv = wave_id(), lane = lane_id();
-#pragma unroll
-  for (int k = 0; k < KB; ++k) acc[k] = 0;
-  if constexpr (KB % 2 == 0 && sizeof(T) == 4) {
-#pragma unroll
-    for (int k = 0; k < KB; k += 2) {
-      const int s0 = k * NW + wv, s1 = (k + 1) * NW + wv;
-      const int o0 = cld(a.off, (unsigned)s0), o1 = cld(a.off, (unsigned)s1);
-      const int wd0 = cld(a.width, (unsigned)s0), wd1 = cld(a.width, (unsigned)s1);
-      const int wd = wd0 > wd1 ? wd0 : wd1;
-      for (int p = 0; p < wd; p += 4) {
-        T v0[4], v1[4];
-        int c0[4], c1[4];
-        const bool r0 = p < wd0, r1 = p < wd1;   // uniform: widths are per slice
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          v0[u] = v1[u] = 0;
-          c0[u] = c1[u] = 0;
-        }
-        if (r0)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const unsigned q = (unsigned)(o0 + (p + u) * WAVE + lane);
-            v0[u] = cld(a.val, q);
-            c0[u] = cld(a.col, q);
-          }
-        if (r1)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const unsigned q = (unsigned)(o1 + (p + u) * WAVE + lane);
-            v1[u] = cld(a.val, q);
-            c1[u] = cld(a.col, q);
-          }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          acc[k] += v0[u] * x[c0[u]];
-          acc[k + 1] += v1[u] * x[c1[u]];
-        }
-      }
-      settle(acc[k]);
-      settle(acc[k + 1]);
-    }
-  } else {
-    sell_slots<KB, NW>(
-        a, [&](int k, T v, int c) { acc[k] += v * x[c]; }, [&](int k) { settle(acc[k]); });
-  }
-}
-
 // One group of four entries of a packed sliced layout (group index g) into
-// v[0..3] and c[0..3].
-template <typename T>
-__device__ __forceinline__ void pgroup(const PSell<T>& a, unsigned g, T* v, int* c) {
+// v[0..3] and c[0..3]: one 8-byte load of the columns and sizeof(V) / 4
+// 16-byte loads of the values.
+template <typename V>
+__device__ __forceinline__ void pgroup(const PSell<V>& a, unsigned g, V* v, int* c) {
   const int2 cc = cld(reinterpret_cast<const int2*>(a.col), g);
   c[0] = cc.x & 0xffff;
   c[1] = (int)((unsigned)cc.x >> 16);
   c[2] = cc.y & 0xffff;
   c[3] = (int)((unsigned)cc.y >> 16);
-  if constexpr (sizeof(T) == 8) {
-    const int4 p = cld(reinterpret_cast<const int4*>(a.val), 2 * g);
-    const int4 q = cld(reinterpret_cast<const int4*>(a.val), 2 * g + 1);
-    __builtin_memcpy(&v[0], &p, 16);
-    __builtin_memcpy(&v[2], &q, 16);
-  } else {
-    const int4 p = cld(reinterpret_cast<const int4*>(a.val), g);
-    __builtin_memcpy(v, &p, 16);
+  constexpr int NL = (int)sizeof(V) / 4;
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int4 q = cld(reinterpret_cast<const int4*>(a.val), (unsigned)NL * g + u);
+    __builtin_memcpy(reinterpret_cast<char*>(v) + 16 * u, &q, 16);
+  }
+}
+
+// One row (slice s, this lane) of a packed layout, a group per round.
+template <typename V, typename Body>
+__device__ __forceinline__ void psell_row(const PSell<V>& a, int s, Body&& body) {
+  const int lane = lane_id();
+  const int o = cld(a.off, (unsigned)s);
+  const int wd = cld(a.width, (unsigned)s);
+  for (int p = 0; p < wd; ++p) {
+    V v[4];
+    int c[4];
+    pgroup(a, (unsigned)(o + p * WAVE + lane), v, c);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) body(v[u], c[u]);
+  }
+}
+
+// Rows by bus slot of a packed layout: the thread's bus slots k < KB are rows
+// of slices k NW + wave.  body(k, val, col) accumulates one entry of slot k;
+// after a slot's row, done(k) runs.
+template <int KB, int NW, typename V, typename Body, typename Done>
+__device__ __forceinline__ void psell_slots(const PSell<V>& a, Body&& body, Done&& done) {
+  const int wv = wave_id();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    psell_row(a, k * NW + wv, [&](V v, int c) { body(k, v, c); });
+    done(k);
   }
 }
 
@@ -423,6 +457,38 @@ __device__ __forceinline__ void sell_slots_store(const PSell<T>& a, const int* r
   }
 }
 
+// acc[k] = sum over slot k's row of val * x[col] for a packed layout by bus
+// slot (slices k NW + wave); rows in rounds of two groups, then one group.
+template <int KB, int NW, typename T>
+__device__ __forceinline__ void psell_slots_dot(const PSell<T>& a, const T* x, T (&acc)[KB]) {
+  const int wv = wave_id(), lane = lane_id();
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    const unsigned sl = (unsigned)(k * NW + wv);
+    const int o = cld(a.off, sl);
+    const int wd = cld(a.width, sl);
+    T s = 0;
+    int p = 0;
+    for (; p + 2 <= wd; p += 2) {
+      T v[8];
+      int c[8];
+      pgroup(a, (unsigned)(o + p * WAVE + lane), v, c);
+      pgroup(a, (unsigned)(o + (p + 1) * WAVE + lane), v + 4, c + 4);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u] * x[c[u]];
+    }
+    if (p < wd) {
+      T v[4];
+      int c[4];
+      pgroup(a, (unsigned)(o + p * WAVE + lane), v, c);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s += v[u] * x[c[u]];
+    }
+    acc[k] = s;
+    settle(acc[k]);
+  }
+}
+
 // out[OFF + k] = (A^-1 x)_i for the bus slots i = t + k BLOCK (zero past N), by
 // the explicit factor passes E1 (rows into `aux` / the core right-hand side
 // into `tmp`), E2 (dense core into aux past c), E3 (rows in matrix order, read
@@ -439,7 +505,7 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
   constexpr int NW = BLOCK / WAVE;
   if (f.direct) {  // one sliced pass over A^-1 itself; no barrier, x read throughout
     T acc[KB];
-    sell_slots_dot<KB, NW>(f.inv, x, acc);
+    psell_slots_dot<KB, NW>(f.inv, x, acc);
 #pragma unroll
     for (int k = 0; k < KB; ++k) out[OFF + k] = acc[k];
     return;
@@ -448,33 +514,24 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
   // (kept rolled: the loop indexes no register array, and its body is large)
 #pragma unroll 1
   for (int q = 0; q < KB; ++q) {
-    // (entry offset, width, first row) of this wave's q-th slice; width 0 past its list
+    // (group offset, width in groups, first row) of this wave's q-th slice; width 0 past its list
     const int4 t = cld(reinterpret_cast<const int4*>(f.e1_wave), (unsigned)(wv * KB + q));
     if (t.y > 0) {
       const int r = cld(f.e1_row, (unsigned)(t.z + lane));
       T acc = 0;
       int p = 0;
-      for (; p + 8 <= t.y; p += 8) {  // eight entries in flight per round while they last
+      for (; p + 2 <= t.y; p += 2) {  // two groups (eight entries) in flight per round while they last
         T v[8];
         int c[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const unsigned qq = (unsigned)(t.x + (p + u) * WAVE + lane);
-          v[u] = cld(f.e1.val, qq);
-          c[u] = cld(f.e1.col, qq);
-        }
+        pgroup(f.e1, (unsigned)(t.x + p * WAVE + lane), v, c);
+        pgroup(f.e1, (unsigned)(t.x + (p + 1) * WAVE + lane), v + 4, c + 4);
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += v[u] * x[c[u]];
       }
-      if (p < t.y) {  // widths are multiples of 4: at most one round of four remains
+      if (p < t.y) {
         T v[4];
         int c[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const unsigned qq = (unsigned)(t.x + (p + u) * WAVE + lane);
-          v[u] = cld(f.e1.val, qq);
-          c[u] = cld(f.e1.col, qq);
-        }
+        pgroup(f.e1, (unsigned)(t.x + p * WAVE + lane), v, c);
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc += v[u] * x[c[u]];
       }
@@ -523,7 +580,7 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
     return;
   }
   T acc[KB];
-  sell_slots_dot<KB, NW>(f.e3, aux, acc);
+  psell_slots_dot<KB, NW>(f.e3, aux, acc);
 #pragma unroll
   for (int k = 0; k < KB; ++k) out[OFF + k] = acc[k];
 }
@@ -544,11 +601,18 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
   const unsigned nth = net.nth, npq = net.npq;
   T* X = s.xs;
   T* Y = s.xs + nth;
+  constexpr int G = Ws<BLOCK, KB>::G;
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    const unsigned i = row<BLOCK>(k);
-    const T v = w[k] * ws.template get_ivm<T>(k);
-    if (i < nth) X[i] = v;
+  for (int k = 0; k < KB; k += G) {
+    T iv[2];
+    if constexpr (G == 2) ws.template get_ivm2<T>(k, iv);
+    else iv[0] = ws.template get_ivm<T>(k);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const unsigned i = row<BLOCK>(k + u);
+      const T v = w[k + u] * iv[u];
+      if (i < nth) X[i] = v;
+    }
   }
   __syncthreads();
   if (net.bp.direct) {
@@ -579,12 +643,18 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
   if (npq > 0) {
     const TxDev<T> nt = load_desc(netp);
     T gz[KB];
-    sell_slots_dot<KB, NW>(nt.g, X, gz);
+    psell_slots_dot<KB, NW>(nt.g, X, gz);
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const unsigned i = row<BLOCK>(k);
-      const T t = (w[KB + k] - gz[k]) * ws.template get_ivm<T>(k);
-      if (i < npq) Y[i] = t;
+    for (int k = 0; k < KB; k += G) {
+      T iv[2];
+      if constexpr (G == 2) ws.template get_ivm2<T>(k, iv);
+      else iv[0] = ws.template get_ivm<T>(k);
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const unsigned i = row<BLOCK>(k + u);
+        const T t = (w[KB + k + u] - gz[k + u]) * iv[u];
+        if (i < npq) Y[i] = t;
+      }
     }
     __syncthreads();
     efac_apply<T, BLOCK, KB, KB>(nt.bpp, Y, X, s.tmp, w);
@@ -605,29 +675,55 @@ __device__ void jvp(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 * KB
   T2* dv = reinterpret_cast<T2*>(lds);
   // dV_i = V_i (j p_theta + p_|V| / |V|).  The input w is dead after this
   // loop, so the own buses' V stays in its registers for the second phase.
+  constexpr int G = Ws<BLOCK, KB>::G;
   T vre[KB], vim[KB];
 #pragma unroll
-  for (int k = 0; k < KB; ++k) {
-    const unsigned i = row<BLOCK>(k);
-    const T a = w[KB + k] * ws.template get_ivm<T>(k);
-    ws.template get_v<T>(k, vre[k], vim[k]);
-    T2 d;
-    d.x = vre[k] * a - vim[k] * w[k];
-    d.y = vim[k] * a + vre[k] * w[k];
-    dv[i] = d;
+  for (int k = 0; k < KB; k += G) {
+    T iv[2];
+    if constexpr (G == 2) {
+      ws.template get_ivm2<T>(k, iv);
+      T re[2], im[2];
+      ws.template get_v2<T>(k, re, im);
+      vre[k] = re[0];
+      vre[k + 1] = re[1];
+      vim[k] = im[0];
+      vim[k + 1] = im[1];
+    } else {
+      iv[0] = ws.template get_ivm<T>(k);
+      ws.template get_v<T>(k, vre[k], vim[k]);
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const unsigned i = row<BLOCK>(k + u);
+      const T a = w[KB + k + u] * iv[u];
+      T2 d;
+      d.x = vre[k + u] * a - vim[k + u] * w[k + u];
+      d.y = vim[k + u] * a + vre[k + u] * w[k + u];
+      dv[i] = d;
+    }
   }
   __syncthreads();
-  // The own bus's I is fetched one slot ahead, so its HBM latency overlaps the
-  // previous slot's row.
+  // The own buses' I is fetched one slot pair ahead, so its HBM latency
+  // overlaps the previous slots' rows.
   const int wv = wave_id();
-  T nIr, nIi;
-  ws.template get_i<T>(0, nIr, nIi);
+  T cIr[2], cIi[2], nIr[2], nIi[2];
+  if constexpr (G == 2) ws.template get_i2<T>(0, nIr, nIi);
+  else ws.template get_i<T>(0, nIr[0], nIi[0]);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const T Ir = nIr, Ii = nIi, vr = vre[k], vi = vim[k];
-    if (k + 1 < KB) ws.template get_i<T>(k + 1, nIr, nIi);
+    if (k % G == 0) {
+      cIr[0] = nIr[0];
+      cIi[0] = nIi[0];
+      cIr[1] = nIr[1];
+      cIi[1] = nIi[1];
+      if (k + G < KB) {
+        if constexpr (G == 2) ws.template get_i2<T>(k + G, nIr, nIi);
+        else ws.template get_i<T>(k + G, nIr[0], nIi[0]);
+      }
+    }
+    const T Ir = cIr[k % G], Ii = cIi[k % G], vr = vre[k], vi = vim[k];
     T dIr = 0, dIi = 0;
-    sell_row4(net.yT, k * NW + wv, [&](T2 y, int c) {
+    psell_row(net.yT, k * NW + wv, [&](T2 y, int c) {
       const T2 d = dv[c];
       dIr += y.x * d.x - y.y * d.y;
       dIi += y.x * d.y + y.y * d.x;
@@ -650,12 +746,19 @@ __device__ void multi_dot(const Basis<T, BLOCK, KB>& basis, int nv, const T (&w)
   constexpr int NW = BLOCK / WAVE;
   const int lane = lane_id(), wid = wave_id();
   int i = 0;
+  constexpr int G = Basis<T, BLOCK, KB>::G;
   for (; i + 1 < nv; i += 2) {  // two vectors per round: twice the loads in flight
     T a0 = 0, a1 = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * KB; ++k) {
-      a0 += basis.ld(i, k) * w[k];
-      a1 += basis.ld(i + 1, k) * w[k];
+    for (int g = 0; g < 2 * KB / G; ++g) {
+      T e0[G], e1[G];
+      basis.ldg(i, g, e0);
+      basis.ldg(i + 1, g, e1);
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        a0 += e0[q] * w[g * G + q];
+        a1 += e1[q] * w[g * G + q];
+      }
     }
     a0 = wave_total(a0);
     a1 = wave_total(a1);
@@ -667,7 +770,12 @@ __device__ void multi_dot(const Basis<T, BLOCK, KB>& basis, int nv, const T (&w)
   if (i < nv) {
     T a0 = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * KB; ++k) a0 += basis.ld(i, k) * w[k];
+    for (int g = 0; g < 2 * KB / G; ++g) {
+      T e0[G];
+      basis.ldg(i, g, e0);
+#pragma unroll
+      for (int q = 0; q < G; ++q) a0 += e0[q] * w[g * G + q];
+    }
     a0 = wave_total(a0);
     if (lane == 0) part[i * NW + wid] = a0;
   }
@@ -688,19 +796,31 @@ __device__ __forceinline__ T part_sum(const T* part, int i) {
 template <typename T, int BLOCK, int KB>
 __device__ T subtract_proj(const Basis<T, BLOCK, KB>& basis, int nv, T (&w)[2 * KB], const T* part) {
   constexpr int NW = BLOCK / WAVE;
+  constexpr int G = Basis<T, BLOCK, KB>::G;
   T hh = 0;
   int i = 0;
   for (; i + 1 < nv; i += 2) {
     const T h0 = part_sum<T, NW>(part, i), h1 = part_sum<T, NW>(part, i + 1);
     hh += h0 * h0 + h1 * h1;
 #pragma unroll
-    for (int k = 0; k < 2 * KB; ++k) w[k] -= h0 * basis.ld(i, k) + h1 * basis.ld(i + 1, k);
+    for (int g = 0; g < 2 * KB / G; ++g) {
+      T e0[G], e1[G];
+      basis.ldg(i, g, e0);
+      basis.ldg(i + 1, g, e1);
+#pragma unroll
+      for (int q = 0; q < G; ++q) w[g * G + q] -= h0 * e0[q] + h1 * e1[q];
+    }
   }
   if (i < nv) {
     const T h0 = part_sum<T, NW>(part, i);
     hh += h0 * h0;
 #pragma unroll
-    for (int k = 0; k < 2 * KB; ++k) w[k] -= h0 * basis.ld(i, k);
+    for (int g = 0; g < 2 * KB / G; ++g) {
+      T e0[G];
+      basis.ldg(i, g, e0);
+#pragma unroll
+      for (int q = 0; q < G; ++q) w[g * G + q] -= h0 * e0[q];
+    }
   }
   return hh;
 }
@@ -740,7 +860,7 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
       nq = ws.ld(QIN, k + 1);
     }
     double Ir = 0.0, Ii = 0.0;
-    sell_row4(net.y64, k * NW + wv, [&](double2 y, int c) {
+    psell_row(net.y64, k * NW + wv, [&](double2 y, int c) {
       const double2 v = vs[c];
       Ir += y.x * v.x - y.y * v.y;
       Ii += y.x * v.y + y.y * v.x;
@@ -801,6 +921,7 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
                            bool* converged, const ByteModel& bm, double* work) {
   constexpr int NW = BLOCK / WAVE;
   constexpr int K = 2 * KB;
+  constexpr int G = Basis<T, BLOCK, KB>::G;
   const unsigned pstride = (unsigned)(R + 2) * NW;
   int par = 0;
   auto next_part = [&]() {
@@ -812,8 +933,12 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
   T beta0 = 0;
   int total = 0;
   bool done = false;
+  {
+    double z[K];
 #pragma unroll
-  for (int k = 0; k < K; ++k) ws.st(xpl, k, 0.0);
+    for (int k = 0; k < K; ++k) z[k] = 0.0;
+    ws.st_all(xpl, z);
+  }
   for (int cycle = 0; cycle < max_restarts && !done; ++cycle) {
     *work += (cycle > 0 ? bm.jvp() : 0.0) + bm.pre() + bm.m8 + bm.wm;
     int steps = 0;
@@ -823,14 +948,13 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
     // steps.  One call site for A and one for M^-1 keeps the loop's code
     // compact (they are inlined).
     for (int j = -1; j < R; ++j) {
-      if (j < 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(cycle == 0 ? bpl : xpl, k);
-      }
+      if (j < 0) ws.ld_all(cycle == 0 ? bpl : xpl, w);
       if (j >= 0 || cycle > 0) apply_a(w);
       if (j < 0 && cycle > 0) {
+        T bv[K];
+        ws.ld_all(bpl, bv);
 #pragma unroll
-        for (int k = 0; k < K; ++k) w[k] = (T)ws.ld(bpl, k) - w[k];
+        for (int k = 0; k < K; ++k) w[k] = bv[k] - w[k];
       }
       apply_m(w);
       if (j < 0) {
@@ -846,10 +970,9 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
         }
         const T ib = (T)1 / beta;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-          w[k] *= ib;
-          basis.st(0, k, w[k]);
-        }
+        for (int k = 0; k < K; ++k) w[k] *= ib;
+#pragma unroll
+        for (int g = 0; g < K / G; ++g) basis.stg(0, g, w + g * G);
         if (threadIdx.x == 0) s.gres[0] = beta;
         res = beta;
         continue;
@@ -916,10 +1039,9 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
       if (!(res > rtol * beta0) || j == R - 1 || !(hn > (T)0)) break;
       const T ih = (T)1 / hn;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        w[k] *= ih;
-        basis.st(j + 1, k, w[k]);
-      }
+      for (int k = 0; k < K; ++k) w[k] *= ih;
+#pragma unroll
+      for (int g = 0; g < K / G; ++g) basis.stg(j + 1, g, w + g * G);
     }
     if (stop) break;
     total += steps;
@@ -938,15 +1060,18 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
     // for all bus slots are in flight together
     {
       double acc[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) acc[k] = ws.ld(xpl, k);
+      ws.ld_all(xpl, acc);
       for (int i = 0; i < steps; ++i) {
         const double yi = (double)s.yv[i];
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += yi * (double)basis.ld(i, k);
-      }
+        for (int g = 0; g < K / G; ++g) {
+          T e[G];
+          basis.ldg(i, g, e);
 #pragma unroll
-      for (int k = 0; k < K; ++k) ws.st(xpl, k, acc[k]);
+          for (int q = 0; q < G; ++q) acc[g * G + q] += yi * (double)e[q];
+        }
+      }
+      ws.st_all(xpl, acc);
     }
     done = !(res > rtol * beta0);
   }
@@ -1084,16 +1209,40 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     }
     fprev = fnorm;
     // right-hand side -F in place (own rows)
+    {
+      constexpr int G = Ws<BLOCK, KB>::G;
 #pragma unroll
-    for (int k = 0; k < K; ++k) ws.st(FP, k, -ws.ld(FP, k));
+      for (int k = 0; k < K; k += G) {
+        if constexpr (G == 2) {
+          double f0, f1;
+          ws.ld2(FP, k, f0, f1);
+          ws.st2(FP, k, -f0, -f1);
+        } else {
+          ws.st(FP, k, -ws.ld(FP, k));
+        }
+      }
+    }
     bool lin_ok;
     gtotal += gmres_solve<T, BLOCK, KB>(apply_j, apply_m, ws, FP, DXP, basis, R, a.max_restarts, (T)rt, s,
                                         &lin_ok, bm, &work);
     // Newton update (eq. (3)), FP64, own buses
+    {
+      constexpr int G = Ws<BLOCK, KB>::G;
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      ws.st(TH, k, ws.ld(TH, k) + ws.ld(DXP, k));
-      ws.st(VM, k, ws.ld(VM, k) + ws.ld(DXP, KB + k));
+      for (int k = 0; k < KB; k += G) {
+        if constexpr (G == 2) {
+          double t0, t1, m0, m1, d0, d1, e0, e1;
+          ws.ld2(TH, k, t0, t1);
+          ws.ld2(VM, k, m0, m1);
+          ws.ld2(DXP, k, d0, d1);
+          ws.ld2(DXP, KB + k, e0, e1);
+          ws.st2(TH, k, t0 + d0, t1 + d1);
+          ws.st2(VM, k, m0 + e0, m1 + e1);
+        } else {
+          ws.st(TH, k, ws.ld(TH, k) + ws.ld(DXP, k));
+          ws.st(VM, k, ws.ld(VM, k) + ws.ld(DXP, KB + k));
+        }
+      }
     }
     work += bm.update();
     ++newton;
@@ -1390,7 +1539,7 @@ __device__ void vjp(const TxDev<double>* netp, const Ws<BLOCK, KB>& ws, double (
       niv = ws.ld(IVM, k + 1);
     }
     double gr = 0.0, gi = 0.0;  // (Y^T (c conj V))_i
-    sell_row4(net.yt, k * NW + wv, [&](double2 y, int c) {
+    psell_row(net.yt, k * NW + wv, [&](double2 y, int c) {
       const double2 t = u[c];
       gr += y.x * t.x - y.y * t.y;
       gi += y.x * t.y + y.y * t.x;
@@ -1438,7 +1587,7 @@ __device__ void precond_t(const TxDev<double>* netp, const Ws<BLOCK, KB>& ws, do
     __syncthreads();
     const TxDev<double> nt = load_desc(netp);
     double gz[KB];
-    sell_slots_dot<KB, NW>(nt.gt, Y, gz);
+    psell_slots_dot<KB, NW>(nt.gt, Y, gz);
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);
@@ -1511,7 +1660,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     double Ir[KB], Ii[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) Ir[k] = Ii[k] = 0.0;
-    sell_slots<KB, NW>(
+    psell_slots<KB, NW>(
         net.y64,
         [&](int k, double2 y, int c) {
           const double2 v = s.vs[c];

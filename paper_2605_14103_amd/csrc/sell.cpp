@@ -67,7 +67,8 @@ void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b) {
   }
 }
 
-void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& b) {
+std::pair<std::vector<int>, std::vector<int>> upload_psell(Context* ctx, const std::vector<SellRow>& rows,
+                                                           PSellBuffers& b, bool cplx) {
   const int ns = (int)rows.size() / SLICE;
   std::vector<int> off(ns), width(ns);
   int cur = 0;
@@ -79,7 +80,7 @@ void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& 
     cur += SLICE * width[s];
   }
   std::vector<unsigned short> col((size_t)4 * cur, 0);
-  std::vector<double> val((size_t)4 * cur, 0.0);
+  std::vector<double> val((size_t)4 * cur, 0.0), vim(cplx ? (size_t)4 * cur : 0, 0.0);
   long entries = 0;
   for (int s = 0; s < ns; ++s)
     for (int l = 0; l < SLICE; ++l) {
@@ -90,6 +91,7 @@ void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& 
         const size_t q = 4 * ((size_t)off[s] + (p / 4) * SLICE + l) + p % 4;
         col[q] = (unsigned short)c;
         val[q] = std::get<1>(r[p]);
+        if (cplx) vim[q] = std::get<2>(r[p]);
       }
       entries += (long)r.size();
     }
@@ -98,8 +100,22 @@ void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& 
   b.off = upload(ctx, off);
   b.width = upload(ctx, width);
   b.col = upload(ctx, col);
-  b.val64 = upload(ctx, val);
-  b.val32 = upload(ctx, std::vector<float>(val.begin(), val.end()));
+  if (cplx) {
+    std::vector<double> v64(2 * val.size());
+    std::vector<float> v32(2 * val.size());
+    for (size_t i = 0; i < val.size(); ++i) {
+      v64[2 * i] = val[i];
+      v64[2 * i + 1] = vim[i];
+      v32[2 * i] = (float)val[i];
+      v32[2 * i + 1] = (float)vim[i];
+    }
+    b.val64 = upload(ctx, v64);
+    b.val32 = upload(ctx, v32);
+  } else {
+    b.val64 = upload(ctx, val);
+    b.val32 = upload(ctx, std::vector<float>(val.begin(), val.end()));
+  }
+  return {off, width};
 }
 
 template <>
@@ -109,6 +125,15 @@ PSell<double> PSellBuffers::view<double>() const {
 template <>
 PSell<float> PSellBuffers::view<float>() const {
   return PSell<float>{off.as<int>(), width.as<int>(), col.as<unsigned short>(), val32.as<float>()};
+}
+
+template <>
+PSell<double2> PSellBuffers::view<double2>() const {
+  return PSell<double2>{off.as<int>(), width.as<int>(), col.as<unsigned short>(), val64.as<double2>()};
+}
+template <>
+PSell<float2> PSellBuffers::view<float2>() const {
+  return PSell<float2>{off.as<int>(), width.as<int>(), col.as<unsigned short>(), val32.as<float2>()};
 }
 
 template <>

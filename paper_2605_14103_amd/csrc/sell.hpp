@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -22,12 +23,13 @@ struct Sell {
   const V* val;
 };
 
-// Packed sliced layout for real values: the slices of Sell, but each lane's
-// entries are grouped in fours.  Group g of the row on lane l of slice s is
-// group index off[s] + 64 g + l; it holds four values (val[4 index ..]) and
-// four 16-bit columns (col[4 index ..]), so a group is one 8-byte column load
-// and one (FP32) or two (FP64) 16-byte value loads.  Offsets and widths count
-// groups; padding entries have column 0 and value 0.
+// Packed sliced layout: the slices of Sell, but each lane's entries are
+// grouped in fours.  Group g of the row on lane l of slice s is group index
+// off[s] + 64 g + l; it holds four values (val[4 index ..]) and four 16-bit
+// columns (col[4 index ..]), so a group is one 8-byte column load and
+// sizeof(V) / 4 16-byte value loads.  Offsets and widths count groups;
+// padding entries have column 0 and value 0.  Entry p of that row is entry
+// 4 (off[s] + 64 (p / 4) + l) + p % 4 of the value array.
 template <typename V>
 struct PSell {
   const int* off;
@@ -73,8 +75,9 @@ SellHost build_sell(const std::vector<SellRow>& rows, int quantum = 1);
 // Device copies: values in FP64 and FP32, complex values as (re, im) pairs.
 void upload_sell(Context* ctx, const SellHost& h, bool cplx, SellBuffers& b);
 
-// Packed layout (real values, columns below 65536) with device copies of its
-// values in FP64 and FP32; rows as for build_sell (a multiple of 64).
+// Packed layout (columns below 65536) with device copies of its values in
+// FP64 and FP32 (complex values as (re, im) pairs); rows as for build_sell (a
+// multiple of 64).
 struct PSellBuffers {
   int n_slices = 0;
   long entries = 0;
@@ -82,6 +85,8 @@ struct PSellBuffers {
   template <typename V>
   PSell<V> view() const;
 };
-void upload_psell(Context* ctx, const std::vector<SellRow>& rows, PSellBuffers& b);
+// Returns the slices' group offsets and widths (as uploaded).
+std::pair<std::vector<int>, std::vector<int>> upload_psell(Context* ctx, const std::vector<SellRow>& rows,
+                                                           PSellBuffers& b, bool cplx = false);
 
 }  // namespace pfx

@@ -33,10 +33,10 @@ namespace pfx {
 template <typename T>
 struct EfDev {
   int N, c, k;
-  Sell<T> e1;
+  PSell<T> e1;
   const int* e1_row;     // [n_slices * 64]
-  const int* e1_wave;    // [n_waves * kb][4]: entry offset, width, first row id index, 0
-  Sell<T> e3;
+  const int* e1_wave;    // [n_waves * kb][4]: group offset, width in groups, first row id index, 0
+  PSell<T> e3;
   // The same E3 rows sorted by length into slices dealt to (slot, wave)
   // positions k NW + w with balanced rounds; e3s_row[slice * 64 + lane] is
   // the row's matrix row (-1 for padding).  Used where the result goes to LDS.
@@ -47,7 +47,7 @@ struct EfDev {
   // pass: then `direct` is 1 and `inv` holds A^-1 by rows in bus order, with
   // columns in matrix order (E1, E2 and E3 are not used).
   int direct;
-  Sell<T> inv;
+  PSell<T> inv;
 };
 
 template <typename T>
@@ -56,11 +56,11 @@ struct TxDev {
   int kb;                // bus slots per thread
   int nbp;               // padded bus count, kb * block
   const int* int2ext;    // internal bus -> caller's bus index
-  Sell<double2> y64;     // Ybus rows by internal bus (FP64 values)
-  Sell<typename Vec2<T>::type> yT;   // the same entries in T (Jacobian-vector products)
-  Sell<double2> yt;      // Ybus^T rows (adjoint)
-  Sell<T> g;             // G = -Re(Ybus)[Q, Theta]: rows PQ buses, columns Theta buses
-  Sell<double> gt;       // G^T: rows Theta buses, columns PQ buses (adjoint)
+  PSell<double2> y64;    // Ybus rows by internal bus (FP64 values)
+  PSell<typename Vec2<T>::type> yT;   // the same entries in T (Jacobian-vector products)
+  PSell<double2> yt;     // Ybus^T rows (adjoint)
+  PSell<T> g;            // G = -Re(Ybus)[Q, Theta]: rows PQ buses, columns Theta buses
+  PSell<double> gt;      // G^T: rows Theta buses, columns PQ buses (adjoint)
   EfDev<T> bp;           // (B' + eps I)^-1 over Theta
   EfDev<T> bpp;          // (B'' + eps I)^-1 over Q
   // branch list (internal bus numbers) for the branch-current loss
@@ -89,9 +89,8 @@ struct DirectDev {
 struct EfBuffers {
   ExplicitFactor host;
   bool direct = false;
-  SellBuffers inv;
-  SellBuffers e1, e3;
-  PSellBuffers e3s;
+  PSellBuffers inv;
+  PSellBuffers e1, e3, e3s;
   DeviceBuffer e1_row, e1_wave, e3s_row, sinv64, sinv32;
   template <typename T>
   EfDev<T> view() const;
@@ -104,7 +103,8 @@ struct TxNetwork {
   std::vector<int> int2ext, ext2int;
   pf_opts setup{};
   DeviceBuffer int2ext_d;
-  SellBuffers y, yt, g, gt;   // y/yt values are complex (re, im pairs)
+  PSellBuffers y, yt;   // values are complex (re, im pairs)
+  PSellBuffers g, gt;
   EfBuffers bp, bpp;
   DeviceBuffer br_f, br_t, br_ys_re, br_ys_im, br_b;
   DeviceBuffer inc_ptr, inc_br;   // branches incident to each internal bus

@@ -38,11 +38,11 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
     rid[q] = r;
     for (auto [j, v] : E.e1[r]) rows1[q].push_back({E.perm[j], v, 0.0});
   }
-  SellHost h1 = build_sell(rows1, 4);
+  const auto [off1, width1] = upload_psell(ctx, rows1, f.e1);   // widths in groups of four entries
   // Slices to waves: longest first, each to the least loaded wave with room.
   std::vector<int> sl(ns1);
   std::iota(sl.begin(), sl.end(), 0);
-  std::stable_sort(sl.begin(), sl.end(), [&](int a, int b) { return h1.width[a] > h1.width[b]; });
+  std::stable_sort(sl.begin(), sl.end(), [&](int a, int b) { return width1[a] > width1[b]; });
   // (the slice list is longest first, so the greedy assignment balances the
   // longest slices first)
   // Per wave and slot: (entry offset, width, first row of the slice, 0);
@@ -54,18 +54,16 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
       if (cnt[w] < kb && (best < 0 || load[w] < load[best])) best = w;
     if (best < 0) fail(PF_INVALID_ARG, "factor does not fit the workgroup layout");
     int* e = &wave_list[((size_t)best * kb + cnt[best]++) * 4];
-    e[0] = h1.off[s];
-    e[1] = h1.width[s];
+    e[0] = off1[s];
+    e[1] = width1[s];
     e[2] = s * SLICE;
-    load[best] += (h1.width[s] + 7) / 8 + 1;   // rounds of up to eight entries, plus the slice's own overhead
+    load[best] += (width1[s] + 1) / 2 + 1;   // rounds of up to two groups, plus the slice's own overhead
   }
   // E3: one row per matrix row (bus order), padded to nbp rows.
   std::vector<Row> rows3(nbp);
   for (int i = 0; i < N; ++i)
     for (auto [p, v] : E.e3[E.pinv[i]]) rows3[i].push_back({p, v, 0.0});
-  SellHost h3 = build_sell(rows3, 4);
-  upload_sell(ctx, h1, false, f.e1);
-  upload_sell(ctx, h3, false, f.e3);
+  upload_psell(ctx, rows3, f.e3);
   {
     // E3 again with its rows sorted by length (the pass that stores its
     // results to LDS rather than to the owning threads' registers): slices of
@@ -110,14 +108,19 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
       for (auto [c, v] : acc) rowsd[i].push_back({c, v, 0.0});
       nnz += (long)acc.size();
     }
-    SellHost hd = build_sell(rowsd, 4);
-    auto padded = [](const SellHost& h) {
+    // stored entries of a sliced layout: 64 lanes times each slice's longest
+    // row rounded up to a group of four
+    auto padded = [](const std::vector<Row>& rows) {
       long t = 0;
-      for (size_t q = 0; q < h.width.size(); ++q) t += 64L * h.width[q];
+      for (size_t s = 0; s < rows.size(); s += SLICE) {
+        size_t w = 1;
+        for (size_t l = s; l < s + SLICE && l < rows.size(); ++l) w = std::max(w, rows[l].size());
+        t += SLICE * (long)((w + 3) / 4 * 4);
+      }
       return t;
     };
-    if (2 * padded(hd) <= 3 * (padded(h1) + padded(h3))) {
-      upload_sell(ctx, hd, false, f.inv);
+    if (2 * padded(rowsd) <= 3 * (padded(rows1) + padded(rows3))) {
+      upload_psell(ctx, rowsd, f.inv);
       f.direct = true;
     }
   }
@@ -209,7 +212,7 @@ EfDev<T> EfBuffers::view() const {
   d.e3s_row = e3s_row.as<int>();
   d.sinv = f64 ? sinv64.as<T>() : sinv32.as<T>();
   d.direct = direct ? 1 : 0;
-  d.inv = direct ? inv.view<T>() : Sell<T>{nullptr, nullptr, nullptr, nullptr};
+  d.inv = direct ? inv.view<T>() : PSell<T>{nullptr, nullptr, nullptr, nullptr};
   return d;
 }
 
@@ -361,18 +364,23 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
         gtr[j].push_back({i, -yre[p], 0.0});
       }
     }
-  const SellHost hy = build_sell(yr, 4);
+  const auto hy = upload_psell(ctx, yr, net->y, true);
   {
     // Layout entry of each caller CSR entry: row i's p-th (sorted) internal
-    // entry sits at off[i / 64] + 64 p + i % 64.
-    const int64_t E = (int64_t)hy.col.size();
+    // entry sits at 4 (off[i / 64] + 64 (p / 4) + i % 64) + p % 4.
+    const std::vector<int>& yoff = hy.first;
+    auto ypos = [&](int i, int p) {
+      return 4 * ((int64_t)yoff[i / 64] + 64 * (int64_t)(p / 4) + i % 64) + p % 4;
+    };
+    int64_t E = 0;
+    for (int w : hy.second) E += 4 * 64 * (int64_t)w;
     std::vector<std::vector<int>> src(E);
     for (int e = 0; e < n_bus; ++e) {
       const int i = net->ext2int[e];
       for (int p = row_ptr[e]; p < row_ptr[e + 1]; ++p) {
         const int j = net->ext2int[col_idx[p]];
         const int* at = std::lower_bound(col.data() + ptr[i], col.data() + ptr[i + 1], j);
-        const int64_t q = hy.off[i / 64] + (int64_t)(at - (col.data() + ptr[i])) * 64 + i % 64;
+        const int64_t q = ypos(i, (int)(at - (col.data() + ptr[i])));
         src[q].push_back(p);
       }
     }
@@ -380,7 +388,7 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
     net->y_col = col;
     net->y_pos.assign(col.size(), 0);
     for (int i = 0; i < n_bus; ++i)
-      for (int p = ptr[i]; p < ptr[i + 1]; ++p) net->y_pos[p] = hy.off[i / 64] + (p - ptr[i]) * 64 + i % 64;
+      for (int p = ptr[i]; p < ptr[i + 1]; ++p) net->y_pos[p] = (int)ypos(i, p - ptr[i]);
     std::vector<int> sp(E + 1, 0), si;
     for (int64_t q = 0; q < E; ++q) {
       si.insert(si.end(), src[q].begin(), src[q].end());
@@ -392,10 +400,9 @@ TxNetwork* tx_network_create(Context* ctx, int n_bus, int nnz, const int32_t* ro
     net->ysrc_ptr = upload(ctx, sp);
     net->ysrc_idx = upload(ctx, si);
   }
-  upload_sell(ctx, hy, true, net->y);
-  upload_sell(ctx, build_sell(ytr, 4), true, net->yt);
-  upload_sell(ctx, build_sell(gr, 4), false, net->g);
-  upload_sell(ctx, build_sell(gtr, 4), false, net->gt);
+  upload_psell(ctx, ytr, net->yt, true);
+  upload_psell(ctx, gr, net->g);
+  upload_psell(ctx, gtr, net->gt);
   net->int2ext_d = upload(ctx, net->int2ext);
 
   std::vector<int> bf(n_branch), bt(n_branch);
