@@ -835,13 +835,18 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
   TxDev<T> net = load_desc(netp);
   if (yv) net.y64.val = yv;
   const unsigned nth = net.nth, npq = net.npq;
+  // every slot's angle and magnitude requested at once (in pairs), then one
+  // slot at a time through sincos
+  double th[KB], vmag[KB];
+  ws.ld_all(TH, th);
+  ws.ld_all(VM, vmag);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     slot_fence();
     const unsigned i = row<BLOCK>(k);
     double sn, cs;
-    sincos(ws.ld(TH, k), &sn, &cs);
-    const double vm = ws.ld(VM, k);
+    sincos(th[k], &sn, &cs);
+    const double vm = vmag[k];
     double2 v;
     v.x = vm * cs;
     v.y = vm * sn;
