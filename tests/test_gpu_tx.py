@@ -79,6 +79,40 @@ def test_tx2000_full_batch_sampled(ctx, precision):
     net.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_tx2000_full_occupancy_repeatable(ctx, precision):
+    """Batches of 512 and 1024 (two and four workgroups per CU) solved twice: every
+    scenario converged and both runs bit-identical, and each scenario of the
+    1024 batch bit-identical to the same scenario solved in a batch of 256.  A
+    workspace written with 16-byte stores once gave a few percent of the
+    scenarios beyond the first workgroup per CU wrong values, different ones
+    from run to run; this is the check that caught it."""
+    from paper_2605_14103_amd import pf
+    grid = tx.make_grid(tx.TX2000)
+    batch = tx.make_batch(grid, tx.TX2000)
+    net = pf.TxNetwork.from_grid(ctx, grid)
+    o = dict(precision=pf.precision(precision))
+    p, q, vm = to_dev(batch.p_inj), to_dev(batch.q_inj), to_dev(batch.vm_set)
+    import torch
+    for B in (512, 1024):
+        a = net.solve(p[:B], q[:B], vm[:B], **o)
+        torch.cuda.synchronize()
+        va = a.v.cpu().numpy()
+        b = net.solve(p[:B], q[:B], vm[:B], **o)
+        torch.cuda.synchronize()
+        say(f"tx2000 {precision} batch {B}: converged {int(a.converged.sum())}, "
+            f"max mismatch {float(a.mismatch.max()):.2e}")
+        assert a.converged.cpu().numpy().all() and b.converged.cpu().numpy().all()
+        np.testing.assert_array_equal(va, b.v.cpu().numpy())
+        np.testing.assert_array_equal(a.gmres_iters.cpu().numpy(), b.gmres_iters.cpu().numpy())
+    # the last quarter of the 1024 batch (fourth workgroup per CU) against the
+    # same scenarios alone in a batch of 256 (one workgroup per CU)
+    c = net.solve(p[768:], q[768:], vm[768:], **o)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(va[768:], c.v.cpu().numpy())
+    net.close()
+
+
 @pytest.mark.parametrize("direct", [0, 1])
 def test_two_bus_closed_form(ctx, direct):
     from paper_2605_14103_amd import pf
