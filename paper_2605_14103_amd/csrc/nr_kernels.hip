@@ -512,10 +512,11 @@ __device__ void efac_apply(const EfDev<T>& f, const T* x, T* aux, T* tmp, T (&ou
   }
   const int lane = lane_id(), wv = wave_id();
   // (kept rolled: the loop indexes no register array, and its body is large)
+  const int nq = f.e1_nq;
 #pragma unroll 1
-  for (int q = 0; q < KB; ++q) {
+  for (int q = 0; q < nq; ++q) {
     // (group offset, width in groups, first row) of this wave's q-th slice; width 0 past its list
-    const int4 t = cld(reinterpret_cast<const int4*>(f.e1_wave), (unsigned)(wv * KB + q));
+    const int4 t = cld(reinterpret_cast<const int4*>(f.e1_wave), (unsigned)(wv * nq + q));
     if (t.y > 0) {
       const int r = cld(f.e1_row, (unsigned)(t.z + lane));
       T acc = 0;
@@ -856,14 +857,12 @@ __device__ double mismatch(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, double
   __syncthreads();
   const int wv = wave_id();
   double fmax = 0.0;
-  double np = ws.ld(PIN, 0), nq = ws.ld(QIN, 0);
+  double pin[KB], qin[KB];
+  ws.ld_all(PIN, pin);
+  ws.ld_all(QIN, qin);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
-    const double pk = np, qk = nq;
-    if (k + 1 < KB) {
-      np = ws.ld(PIN, k + 1);
-      nq = ws.ld(QIN, k + 1);
-    }
+    const double pk = pin[k], qk = qin[k];
     double Ir = 0.0, Ii = 0.0;
     psell_row(net.y64, k * NW + wv, [&](double2 y, int c) {
       const double2 v = vs[c];
@@ -1120,21 +1119,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   // scheduled injections in internal order (padding buses: |V| = 1, no injection)
   if (phase == 0) {
     const TxDev<T> net = load_desc(netp);
+    // every slot's inputs gathered before any workspace store (the stores
+    // would otherwise hold back the next slot's loads)
+    double p[KB], q[KB], vs[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const unsigned i = row<BLOCK>(k);
-      double p = 0.0, q = 0.0, vs = 1.0;
+      p[k] = 0.0;
+      q[k] = 0.0;
+      vs[k] = 1.0;
       if ((int)i < n) {
         const unsigned e = (unsigned)cld(net.int2ext, i) * 8u;
-        p = bld<double>(P, e, 0);
-        q = bld<double>(Q, e, 0);
-        if ((int)i >= npq) vs = bld<double>(VS, e, 0);
+        p[k] = bld<double>(P, e, 0);
+        q[k] = bld<double>(Q, e, 0);
+        if ((int)i >= npq) vs[k] = bld<double>(VS, e, 0);
       }
-      ws.st(TH, k, 0.0);
-      ws.st(VM, k, vs);
-      ws.st(PIN, k, p);
-      ws.st(QIN, k, q);
     }
+    double zero[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) zero[k] = 0.0;
+    ws.st_all(TH, zero);
+    ws.st_all(VM, vs);
+    ws.st_all(PIN, p);
+    ws.st_all(QIN, q);
   }
 
   using T2 = typename Vec2<T>::type;

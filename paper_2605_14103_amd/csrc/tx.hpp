@@ -35,7 +35,8 @@ struct EfDev {
   int N, c, k;
   PSell<T> e1;
   const int* e1_row;     // [n_slices * 64]
-  const int* e1_wave;    // [n_waves * kb][4]: group offset, width in groups, first row id index, 0
+  const int* e1_wave;    // [n_waves * e1_nq][4]: group offset, width in groups, first row id index, 0
+  int e1_nq;             // entries per wave in e1_wave
   PSell<T> e3;
   // The same E3 rows sorted by length into slices dealt to (slot, wave)
   // positions k NW + w with balanced rounds; e3s_row[slice * 64 + lane] is
@@ -92,6 +93,7 @@ struct EfBuffers {
   PSellBuffers inv;
   PSellBuffers e1, e3, e3s;
   DeviceBuffer e1_row, e1_wave, e3s_row, sinv64, sinv32;
+  int e1_nq = 0;
   template <typename T>
   EfDev<T> view() const;
 };

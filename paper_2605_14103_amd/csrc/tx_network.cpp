@@ -44,21 +44,28 @@ void upload_factor(Context* ctx, EfBuffers& f, int block, int kb, int nbp) {
   std::iota(sl.begin(), sl.end(), 0);
   std::stable_sort(sl.begin(), sl.end(), [&](int a, int b) { return width1[a] > width1[b]; });
   // (the slice list is longest first, so the greedy assignment balances the
-  // longest slices first)
-  // Per wave and slot: (entry offset, width, first row of the slice, 0);
+  // longest slices first; a wave may take any number of slices, so the one
+  // with the longest slice takes few others)
+  // Per wave, e1_nq entries: (group offset, width, first row of the slice, 0);
   // width 0 past the wave's list.
-  std::vector<int> load(nw, 0), cnt(nw, 0), wave_list((size_t)nw * kb * 4, 0);
+  std::vector<int> load(nw, 0), cnt(nw, 0), owner(ns1, 0), slot(ns1, 0);
   for (int s : sl) {
-    int best = -1;
-    for (int w = 0; w < nw; ++w)
-      if (cnt[w] < kb && (best < 0 || load[w] < load[best])) best = w;
-    if (best < 0) fail(PF_INVALID_ARG, "factor does not fit the workgroup layout");
-    int* e = &wave_list[((size_t)best * kb + cnt[best]++) * 4];
+    int best = 0;
+    for (int w = 1; w < nw; ++w)
+      if (load[w] < load[best]) best = w;
+    owner[s] = best;
+    slot[s] = cnt[best]++;
+    load[best] += (width1[s] + 1) / 2 + 1;   // rounds of up to two groups, plus the slice's own overhead
+  }
+  const int nq1 = std::max(1, *std::max_element(cnt.begin(), cnt.end()));
+  std::vector<int> wave_list((size_t)nw * nq1 * 4, 0);
+  for (int s = 0; s < ns1; ++s) {
+    int* e = &wave_list[((size_t)owner[s] * nq1 + slot[s]) * 4];
     e[0] = off1[s];
     e[1] = width1[s];
     e[2] = s * SLICE;
-    load[best] += (width1[s] + 1) / 2 + 1;   // rounds of up to two groups, plus the slice's own overhead
   }
+  f.e1_nq = nq1;
   // E3: one row per matrix row (bus order), padded to nbp rows.
   std::vector<Row> rows3(nbp);
   for (int i = 0; i < N; ++i)
@@ -207,6 +214,7 @@ EfDev<T> EfBuffers::view() const {
   d.e1 = e1.view<T>();
   d.e1_row = e1_row.as<int>();
   d.e1_wave = e1_wave.as<int>();
+  d.e1_nq = e1_nq;
   d.e3 = e3.view<T>();
   d.e3s = e3s.view<T>();
   d.e3s_row = e3s_row.as<int>();
