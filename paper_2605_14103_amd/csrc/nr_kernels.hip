@@ -1222,39 +1222,29 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     fprev = fnorm;
     // right-hand side -F in place (own rows)
     {
-      constexpr int G = Ws<BLOCK, KB>::G;
+      double f[K];
+      ws.ld_all(FP, f);
 #pragma unroll
-      for (int k = 0; k < K; k += G) {
-        if constexpr (G == 2) {
-          double f0, f1;
-          ws.ld2(FP, k, f0, f1);
-          ws.st2(FP, k, -f0, -f1);
-        } else {
-          ws.st(FP, k, -ws.ld(FP, k));
-        }
-      }
+      for (int k = 0; k < K; ++k) f[k] = -f[k];
+      ws.st_all(FP, f);
     }
     bool lin_ok;
     gtotal += gmres_solve<T, BLOCK, KB>(apply_j, apply_m, ws, FP, DXP, basis, R, a.max_restarts, (T)rt, s,
                                         &lin_ok, bm, &work);
     // Newton update (eq. (3)), FP64, own buses
     {
-      constexpr int G = Ws<BLOCK, KB>::G;
+      // every load before the first store (a store holds back later loads)
+      double th[KB], vm[KB], dx[K];
+      ws.ld_all(TH, th);
+      ws.ld_all(VM, vm);
+      ws.ld_all(DXP, dx);
 #pragma unroll
-      for (int k = 0; k < KB; k += G) {
-        if constexpr (G == 2) {
-          double t0, t1, m0, m1, d0, d1, e0, e1;
-          ws.ld2(TH, k, t0, t1);
-          ws.ld2(VM, k, m0, m1);
-          ws.ld2(DXP, k, d0, d1);
-          ws.ld2(DXP, KB + k, e0, e1);
-          ws.st2(TH, k, t0 + d0, t1 + d1);
-          ws.st2(VM, k, m0 + e0, m1 + e1);
-        } else {
-          ws.st(TH, k, ws.ld(TH, k) + ws.ld(DXP, k));
-          ws.st(VM, k, ws.ld(VM, k) + ws.ld(DXP, KB + k));
-        }
+      for (int k = 0; k < KB; ++k) {
+        th[k] += dx[k];
+        vm[k] += dx[KB + k];
       }
+      ws.st_all(TH, th);
+      ws.st_all(VM, vm);
     }
     work += bm.update();
     ++newton;
