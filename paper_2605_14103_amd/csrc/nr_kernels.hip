@@ -643,19 +643,26 @@ __device__ void precond(const TxDev<T>* netp, const Ws<BLOCK, KB>& ws, T (&w)[2 
   }
   if (npq > 0) {
     const TxDev<T> nt = load_desc(netp);
+    // 1/|V| requested before the G pass, so its latency overlaps the pass
+    T iv[KB];
+#pragma unroll
+    for (int k = 0; k < KB; k += G) {
+      if constexpr (G == 2) {
+        T t[2];
+        ws.template get_ivm2<T>(k, t);
+        iv[k] = t[0];
+        iv[k + 1] = t[1];
+      } else {
+        iv[k] = ws.template get_ivm<T>(k);
+      }
+    }
     T gz[KB];
     psell_slots_dot<KB, NW>(nt.g, X, gz);
 #pragma unroll
-    for (int k = 0; k < KB; k += G) {
-      T iv[2];
-      if constexpr (G == 2) ws.template get_ivm2<T>(k, iv);
-      else iv[0] = ws.template get_ivm<T>(k);
-#pragma unroll
-      for (int u = 0; u < G; ++u) {
-        const unsigned i = row<BLOCK>(k + u);
-        const T t = (w[KB + k + u] - gz[k + u]) * iv[u];
-        if (i < npq) Y[i] = t;
-      }
+    for (int k = 0; k < KB; ++k) {
+      const unsigned i = row<BLOCK>(k);
+      const T t = (w[KB + k] - gz[k]) * iv[k];
+      if (i < npq) Y[i] = t;
     }
     __syncthreads();
     efac_apply<T, BLOCK, KB, KB>(nt.bpp, Y, X, s.tmp, w);
@@ -1065,7 +1072,22 @@ __device__ int gmres_solve(ApplyA&& apply_a, ApplyM&& apply_m, const Ws<BLOCK, K
     {
       double acc[K];
       ws.ld_all(xpl, acc);
-      for (int i = 0; i < steps; ++i) {
+      int i = 0;
+      for (; i + 1 < steps; i += 2) {  // two vectors' loads in flight per round
+        const double y0 = (double)s.yv[i], y1 = (double)s.yv[i + 1];
+#pragma unroll
+        for (int g = 0; g < K / G; ++g) {
+          T e0[G], e1[G];
+          basis.ldg(i, g, e0);
+          basis.ldg(i + 1, g, e1);
+#pragma unroll
+          for (int q = 0; q < G; ++q) {
+            acc[g * G + q] += y0 * (double)e0[q];
+            acc[g * G + q] += y1 * (double)e1[q];
+          }
+        }
+      }
+      if (i < steps) {
         const double yi = (double)s.yv[i];
 #pragma unroll
         for (int g = 0; g < K / G; ++g) {
