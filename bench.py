@@ -527,10 +527,12 @@ def bench_adjoint(steps: int, warmup: int) -> dict:
 
 
 def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20, 1, 2), half: bool = True,
-                  forcing: int = 0) -> dict:
+                  forcing: int = 0, feeder_sparse: int = 0) -> dict:
     """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder).
 
-    streams and step_iters are per engine (30-bus, 2000-bus, feeder)."""
+    streams and step_iters are per engine (30-bus, 2000-bus, feeder);
+    feeder_sparse = 1 runs the feeder engine's update by the sparse factor of
+    Y_NN instead of the dense Z product."""
     from paper_2605_14103_amd import pf, serve
     from workloads import feeder as fdm
     from workloads import serving as wsv
@@ -560,9 +562,10 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20
         nets = [pf.TxNetwork.from_grid(ctx, g30), pf.TxNetwork.from_grid(ctx, g2k),
                 pf.DistNetwork.from_feeder(ctx, fd)]
         budgets = (1 << 30, 24 << 30, 4 << 30)
+        extra = ({}, {}, {"zbus_sparse": feeder_sparse})
         engines = [pf.Engine(n, hbm_bytes=b, n_streams=s, precision=pf.precision(prec), step_iters=k,
-                             forcing=forcing)
-                   for n, b, s, k in zip(nets, budgets, streams, step_iters)]
+                             forcing=forcing, **x)
+                   for n, b, s, k, x in zip(nets, budgets, streams, step_iters, extra)]
         # warm-up: one small request per engine (code objects, first launches)
         warm = [r for r in wsv.make_trace(wsv.SERVING, n_requests=30, lam=lam) if r.n_scen <= 8][:6]
         serve.replay(engines, warm, inputs, speed=100.0)
@@ -587,7 +590,8 @@ def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20
             "data": "synthetic",
             "config": {"workload": f"serving mix: Poisson lambda={lam}/s, {n_requests} requests over tx30, "
                                    f"tx2000 and feeder300, 1-512 scenarios each, tol 1e-8",
-                       "streams": list(streams), "step_iters": list(step_iters), "forcing": forcing},
+                       "streams": list(streams), "step_iters": list(step_iters), "forcing": forcing,
+                       "feeder_update": "sparse Y_NN factor" if feeder_sparse else "dense Z product"},
             "latency_ms": {"p50": r["p50_ms"], "p99": r["p99_ms"]},
             "fp64": out["fp64"], "mixed": out["mixed"], "fp64_half_load": out.get("fp64_half_load")}
 
@@ -699,6 +703,9 @@ def main() -> int:
     ap.add_argument("--no-half", action="store_true", help="serving: skip the half-load replay")
     ap.add_argument("--forcing", type=int, default=0,
                     help="serving engines: fixed (0, lower tail latency) or adaptive (1) forcing term")
+    ap.add_argument("--feeder-update", choices=("sparse", "dense"), default="sparse",
+                    help="serving: the feeder engine's update, by the sparse factor of Y_NN (lower latency "
+                         "at the small batches a serving step holds) or the dense Z product")
     ap.add_argument("--cpu-samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
@@ -730,7 +737,8 @@ def main() -> int:
         line = bench_adjoint(a.steps, a.warmup)
     elif a.workload == "serving":
         line = bench_serving(a.requests, a.lam, tuple(int(x) for x in a.streams.split(",")),
-                             tuple(int(x) for x in a.step_iters.split(",")), half=not a.no_half, forcing=a.forcing)
+                             tuple(int(x) for x in a.step_iters.split(",")), half=not a.no_half, forcing=a.forcing,
+                             feeder_sparse=int(a.feeder_update == "sparse"))
     elif a.workload == "sweep":
         line = bench_sweep(a.steps, a.warmup)
     elif a.workload == "feeder_sizes":
@@ -769,7 +777,8 @@ def all_configs(a) -> dict:
                     ("serving_mix", lambda: bench_serving(a.requests, a.lam,
                                                           tuple(int(x) for x in a.streams.split(",")),
                                                           tuple(int(x) for x in a.step_iters.split(",")),
-                                                          forcing=a.forcing))):
+                                                          forcing=a.forcing,
+                                                          feeder_sparse=int(a.feeder_update == "sparse")))):
         t = time.perf_counter()
         try:
             out[key] = _sub(fn())

@@ -416,10 +416,13 @@ pf_status pf_engine_harvest(pf_engine* engine, int32_t n, const int32_t* slot_id
                             int32_t* iters, uint8_t* converged, double* final_mismatch, pf_stream stream);
 
 /* Request-driven engines.  Queue request `id` (caller-chosen, unique among
- * unfetched requests) of n scenarios.  Host inputs, copied before return,
- * [n][row]: transmission: in0 = p_inj, in1 = q_inj, in2 = vm_set (row =
- * n_bus, as in pf_tx_solve); feeder: in0 = s_wye, in1 = s_delta complex
- * (row = 2 n_node doubles, as in pf_dist_solve), in2 unused.
+ * unfetched requests) of n scenarios.  Host inputs [n][row]: transmission:
+ * in0 = p_inj, in1 = q_inj, in2 = vm_set (row = n_bus, as in pf_tx_solve);
+ * feeder: in0 = s_wye, in1 = s_delta complex (row = 2 n_node doubles, as in
+ * pf_dist_solve), in2 unused.  Nothing is copied at submission: the engine
+ * reads the inputs when it admits the request into slots, so the caller
+ * keeps them valid and unchanged until pf_engine_poll reports the request
+ * (or the engine is destroyed).
  * Errors: PF_NOT_ADMITTED (n exceeds the engine's slots), PF_INVALID_ARG
  * (caller-driven engine, n < 1, duplicate id, null input). */
 pf_status pf_engine_submit(pf_engine* engine, int64_t id, int32_t n, const double* in0, const double* in1,

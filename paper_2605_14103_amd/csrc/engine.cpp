@@ -49,10 +49,54 @@ namespace {
 // before admission waits for it.
 constexpr int kMaxBypass = 8;
 
+// Recycled host buffers for requests' results.  A large request's first
+// touch of fresh pages costs more than copying its data (about 0.5 ms per MB
+// against 0.1), and submit runs on the caller's thread, so buffers released
+// by fetched requests are kept (up to kPoolBytes) and handed out again, the
+// closest capacity that fits (if not over four times the size asked for).
+// Inputs are not copied at submission at all: admission reads them from the
+// caller's arrays straight into the pinned slot rows.
+constexpr size_t kPoolBytes = size_t(2) << 30;
+
+class BufferPool {
+ public:
+  std::vector<double> get(size_t n) {
+    std::vector<double> v;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = free_.lower_bound(n);
+      if (it != free_.end() && it->first <= 4 * n + 65536) {   // a small request leaves big buffers alone
+        v = std::move(it->second);
+        bytes_ -= it->first * sizeof(double);
+        free_.erase(it);
+      }
+    }
+    v.resize(n);  // within the capacity: no new pages (a grown tail is zeroed)
+    return v;
+  }
+  void put(std::vector<double>& v) {
+    const size_t cap = v.capacity();
+    if (cap == 0) return;
+    std::lock_guard<std::mutex> lk(mu_);
+    if (bytes_ + cap * sizeof(double) > kPoolBytes) {
+      std::vector<double>().swap(v);
+      return;
+    }
+    bytes_ += cap * sizeof(double);
+    free_.emplace(cap, std::move(v));
+    v = std::vector<double>();
+  }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, std::vector<double>> free_;   // by capacity
+  size_t bytes_ = 0;
+};
+
 struct Request {
   int64_t id = 0;
   int n = 0;
-  std::vector<double> in[3];
+  const double* in[3] = {nullptr, nullptr, nullptr};   // the caller's inputs, read at admission
   int left = 0;        // scenarios not yet harvested
   int bypassed = 0;
   bool admitted = false;
@@ -159,6 +203,7 @@ struct Engine {
   std::deque<int64_t> pending;
   std::map<int64_t, Request> reqs;
   std::deque<int64_t> completed;
+  BufferPool pool;             // request results (own lock)
   bool stop = false;
   uint64_t n_steps = 0, n_scen = 0;
 
@@ -167,7 +212,9 @@ struct Engine {
   std::vector<int> step(Cohort& c, int iters, hipStream_t s);
   void collect(Cohort& c, std::vector<int> slots, hipStream_t s);
   bool can_admit() const;
-  std::vector<int> admit_pending();
+  std::vector<int> admit_pending(std::vector<std::pair<const Request*, int>>& copies);
+  void stage_rows(const std::vector<int>& slots, const std::vector<std::pair<const Request*, int>>& copies);
+  void hand_over(const std::vector<int>& slots);
   void complete(const std::vector<int>& slots, const std::string& err);
   void cohort_loop(int ci);
   int occupied() const { return max_slots - (int)free_slots.size(); }
@@ -416,10 +463,12 @@ bool Engine::can_admit() const {
   return false;
 }
 
-// Under mu: takes waiting requests, in order, into free slots (lowest first)
-// and stages their inputs in the pinned rows.  Returns the slots taken.
-std::vector<int> Engine::admit_pending() {
+// Under mu: takes waiting requests, in order, into free slots (lowest first).
+// Returns the slots taken and, for each, the request and scenario whose
+// inputs stage_rows copies into the slot's pinned row.
+std::vector<int> Engine::admit_pending(std::vector<std::pair<const Request*, int>>& copies) {
   std::vector<int> taken;
+  copies.clear();
   auto it = pending.begin();
   while (it != pending.end() && !free_slots.empty()) {
     Request& r = reqs.at(*it);
@@ -442,31 +491,57 @@ std::vector<int> Engine::admit_pending() {
       slot_st[s] = 1;
       slot_req[s] = r.id;
       slot_idx[s] = q;
-      for (int i = 0; i < n_in; ++i)
-        std::memcpy(in_h[i] + (size_t)s * row, r.in[i].data() + (size_t)q * row, sizeof(double) * row);
+      copies.emplace_back(&r, q);
       taken.push_back(s);
     }
-    for (auto& in : r.in) std::vector<double>().swap(in);
     it = pending.erase(it);
   }
   return taken;
 }
 
-// Under mu: hands the harvested slots' results (pinned rows) to their
-// requests, frees the slots, completes requests whose last scenario this was.
+// Without mu: the admitted scenarios' inputs, from the callers' arrays into
+// the slots' pinned rows.  The slots and their rows are this cohort's alone,
+// and a request stays in the table (its entry does not move) until fetched,
+// which cannot happen before its scenarios finish.
+void Engine::stage_rows(const std::vector<int>& slots,
+                        const std::vector<std::pair<const Request*, int>>& copies) {
+  for (size_t k = 0; k < slots.size(); ++k) {
+    const Request& r = *copies[k].first;
+    const int q = copies[k].second, s = slots[k];
+    for (int i = 0; i < n_in; ++i)
+      std::memcpy(in_h[i] + (size_t)s * row, r.in[i] + (size_t)q * row, sizeof(double) * row);
+  }
+}
+
+// Without mu: the harvested slots' results (pinned rows) into their
+// requests.  The slots are still occupied, so their rows and the requests'
+// entries stay put; slot_req and slot_idx of an occupied slot change only
+// under this cohort's own control.
+void Engine::hand_over(const std::vector<int>& slots) {
+  std::vector<std::pair<Request*, int>> to;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    to.reserve(slots.size());
+    for (int s : slots) to.emplace_back(&reqs.at(slot_req[s]), slot_idx[s]);
+  }
+  for (size_t k = 0; k < slots.size(); ++k) {
+    Request& r = *to[k].first;
+    const int q = to[k].second, s = slots[k];
+    std::memcpy(r.v.data() + (size_t)q * vrow, v_h + (size_t)s * vrow, sizeof(double) * vrow);
+    r.iters[q] = iters_h[s];
+    r.conv[q] = conv_h[s];
+    r.mismatch[q] = mis_h[s];
+  }
+}
+
+// Under mu: frees the harvested slots (their results already handed over,
+// unless the step failed) and completes requests whose last scenario this
+// was.
 void Engine::complete(const std::vector<int>& slots, const std::string& err) {
   const double t = now();
   for (int s : slots) {
     Request& r = reqs.at(slot_req[s]);
-    const int q = slot_idx[s];
-    if (err.empty()) {
-      std::memcpy(r.v.data() + (size_t)q * vrow, v_h + (size_t)s * vrow, sizeof(double) * vrow);
-      r.iters[q] = iters_h[s];
-      r.conv[q] = conv_h[s];
-      r.mismatch[q] = mis_h[s];
-    } else if (r.error.empty()) {
-      r.error = err;
-    }
+    if (!err.empty() && r.error.empty()) r.error = err;
     slot_st[s] = 0;
     slot_req[s] = -1;
     free_slots.insert(s);
@@ -484,18 +559,23 @@ void Engine::cohort_loop(int ci) {
   Cohort& c = cohorts[ci];
   for (;;) {
     std::vector<int> admitted;
+    std::vector<std::pair<const Request*, int>> copies;
     {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !c.active.empty() || can_admit(); });
       if (stop) return;
-      admitted = admit_pending();
+      admitted = admit_pending(copies);
     }
     std::vector<int> done;
     std::string err;
     try {
+      // the large host copies run outside the lock, so submissions and the
+      // other cohorts' admissions never wait for them
+      stage_rows(admitted, copies);
       stage_in(c, admitted, c.stream);
       done = step(c, opts.step_iters, c.stream);
       collect(c, done, c.stream);
+      hand_over(done);
     } catch (const std::exception& e) {
       // a failed step fails every request with a scenario in this cohort
       // (admitted slots included, whether or not staging got to add them)
@@ -542,9 +622,9 @@ void engine_submit(Engine* e, int64_t id, int n, const double* in0, const double
   r.t_submit = e->now();
   for (int i = 0; i < e->n_in; ++i) {
     require(ins[i] != nullptr, "null input array");
-    r.in[i].assign(ins[i], ins[i] + (size_t)n * e->row);
+    r.in[i] = ins[i];
   }
-  r.v.assign((size_t)n * e->vrow, 0.0);
+  r.v = e->pool.get((size_t)n * e->vrow);   // every row is written when its scenario is harvested
   r.iters.assign(n, 0);
   r.conv.assign(n, 0);
   r.mismatch.assign(n, 0.0);
@@ -577,15 +657,20 @@ int engine_request_size(Engine* e, int64_t id) {
 
 void engine_fetch(Engine* e, int64_t id, double* v_out, int32_t* iters, uint8_t* conv, double* mismatch,
                   double* times) {
-  std::lock_guard<std::mutex> lk(e->mu);
-  auto it = e->reqs.find(id);
-  require(it != e->reqs.end(), "unknown request id");
-  Request& r = it->second;
-  require(r.done, "request not finished");
-  if (!r.error.empty()) {
-    const std::string msg = r.error;
+  // The request leaves the table under the lock; its results are copied out
+  // after, so a large copy does not hold up the cohorts' admissions.
+  Request r;
+  {
+    std::lock_guard<std::mutex> lk(e->mu);
+    auto it = e->reqs.find(id);
+    require(it != e->reqs.end(), "unknown request id");
+    require(it->second.done, "request not finished");
+    r = std::move(it->second);
     e->reqs.erase(it);
-    fail(PF_HIP_ERROR, "request failed: " + msg);
+  }
+  if (!r.error.empty()) {
+    e->pool.put(r.v);
+    fail(PF_HIP_ERROR, "request failed: " + r.error);
   }
   if (v_out) std::memcpy(v_out, r.v.data(), sizeof(double) * r.v.size());
   if (iters) std::memcpy(iters, r.iters.data(), 4 * r.iters.size());
@@ -596,7 +681,7 @@ void engine_fetch(Engine* e, int64_t id, double* v_out, int32_t* iters, uint8_t*
     times[1] = r.t_launch;
     times[2] = r.t_done;
   }
-  e->reqs.erase(it);
+  e->pool.put(r.v);
 }
 
 void engine_info(Engine* e, int32_t* max_slots, uint64_t* slot_bytes, int32_t* queued, int32_t* occupied,

@@ -350,6 +350,7 @@ class Engine:
         h = c_void_p()
         L.call("pf_engine_create", network.ctx.h, tx, dist, int(hbm_bytes), int(n_streams), byref(self._o), byref(h))
         self.h = h
+        self._held: dict[int, list] = {}   # submitted requests' input arrays, until fetched
 
     def _inputs(self, inputs) -> tuple[int, list, list]:
         want = 3 if self.kind == "tx" else 2
@@ -364,9 +365,14 @@ class Engine:
         return n, arrs, [_hptr(a) for a in arrs] + [None] * (3 - want)
 
     def submit(self, rid: int, *inputs: np.ndarray) -> None:
-        """Queue request ``rid``: (p, q, vm) float64 (n, n_bus) or (s_wye, s_delta) complex128 (n, n_node)."""
-        n, _arrs, ptrs = self._inputs(inputs)
+        """Queue request ``rid``: (p, q, vm) float64 (n, n_bus) or (s_wye, s_delta) complex128 (n, n_node).
+
+        The engine reads the inputs when it admits the request; the arrays
+        (or their contiguous copies) are held here until the request is
+        fetched.  The caller must not change them before that."""
+        n, arrs, ptrs = self._inputs(inputs)
         L.call("pf_engine_submit", self.h, int(rid), n, *ptrs)
+        self._held[int(rid)] = arrs
 
     def admit(self, slots, *inputs: np.ndarray, stream=None) -> None:
         """Caller-driven: place scenarios (inputs as for ``submit``) into free ``slots``."""
@@ -408,8 +414,14 @@ class Engine:
         res = EngineResult(v=np.empty((n, self.row), dtype=np.complex128), iters=np.empty(n, dtype=np.int32),
                            converged=np.empty(n, dtype=np.uint8), mismatch=np.empty(n),
                            times=np.empty(3))
-        L.call("pf_engine_fetch", self.h, int(rid), _hptr(res.v), _hptr(res.iters), _hptr(res.converged),
-               _hptr(res.mismatch), _hptr(res.times))
+        try:
+            L.call("pf_engine_fetch", self.h, int(rid), _hptr(res.v), _hptr(res.iters), _hptr(res.converged),
+                   _hptr(res.mismatch), _hptr(res.times))
+        except L.PfError as e:
+            if e.status == L.PF_HIP_ERROR:   # the engine forgot the failed request
+                self._held.pop(int(rid), None)
+            raise
+        self._held.pop(int(rid), None)
         return res
 
     def info(self) -> dict:
@@ -423,6 +435,7 @@ class Engine:
         if self.h:
             L.lib().pf_engine_destroy(self.h)
             self.h = c_void_p()
+        self._held = {}
 
     def __del__(self):
         try:

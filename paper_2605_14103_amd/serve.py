@@ -13,6 +13,7 @@ engine's own clock) fields, plus ``info()``.
 """
 from __future__ import annotations
 
+import sys
 import threading
 import time
 from dataclasses import dataclass, field
@@ -72,13 +73,18 @@ class ReplayStats:
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "max_ms": float(lat.max() * 1e3),
             "mean_submit_lag_ms": float(np.mean([s.submit_lag for s in self.served]) * 1e3) if self.served else 0.0,
+            # the parts of the latency, each at its own 50th and 99th percentile
+            "parts_ms": {k: {"p50": float(np.percentile(x, 50) * 1e3), "p99": float(np.percentile(x, 99) * 1e3)}
+                         for k, x in (("submit_lag", [s.submit_lag for s in self.served] or [0.0]),
+                                      ("queue", [s.queue for s in self.served] or [0.0]),
+                                      ("service", [s.service for s in self.served] or [0.0]))},
             "per_network": nets,
             "tol": tol,
         }
 
 
 def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
-           timeout_s: float = 120.0) -> ReplayStats:
+           timeout_s: float = 120.0, switch_interval: float = 2e-4) -> ReplayStats:
     """Play ``trace`` (requests with rid, t_arrive, network, n_scen) against ``engines``.
 
     ``inputs(req)`` returns the request's input arrays (host).  ``speed`` > 1
@@ -86,7 +92,10 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
     after the last arrival are reported as failed.  One thread submits each
     request when its arrival time comes; a second thread harvests finished
     requests (poll, fetch, accounting), so fetching large results never
-    delays a submission.
+    delays a submission.  While the trace plays, the interpreter's thread
+    switch interval is ``switch_interval`` seconds (Python's default is 5
+    ms, which a sleeping submitter could otherwise wait for while the
+    harvester runs Python code).
     """
     order = sorted(trace, key=lambda r: r.t_arrive)
     pending: dict[tuple[int, int], tuple] = {}
@@ -136,23 +145,31 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
                     return
             harvest_once(0.001)
 
-    th = threading.Thread(target=harvester, daemon=True)
-    th.start()
-    for req, arrays in staged:
-        ahead = req.t_arrive / speed - (time.perf_counter() - t0)
-        if ahead > 0:
-            time.sleep(ahead)   # releases the interpreter lock to the harvester
-        eng = engines[req.network]
-        with lock:
-            pending[(req.network, req.rid)] = (req, time.perf_counter() - t0)
-        try:
-            eng.submit(req.rid, *arrays)
-        except Exception as e:     # e.g. a request larger than the engine's slots
+    def play() -> None:
+        th = threading.Thread(target=harvester, daemon=True)
+        th.start()
+        for req, arrays in staged:
+            ahead = req.t_arrive / speed - (time.perf_counter() - t0)
+            if ahead > 0:
+                time.sleep(ahead)   # releases the interpreter lock to the harvester
+            eng = engines[req.network]
             with lock:
-                pending.pop((req.network, req.rid))
-                stats.failed.append((req.rid, str(e)))
-    submitted_all.set()
-    th.join()
+                pending[(req.network, req.rid)] = (req, time.perf_counter() - t0)
+            try:
+                eng.submit(req.rid, *arrays)
+            except Exception as e:     # e.g. a request larger than the engine's slots
+                with lock:
+                    pending.pop((req.network, req.rid))
+                    stats.failed.append((req.rid, str(e)))
+        submitted_all.set()
+        th.join()
+
+    old_switch = sys.getswitchinterval()
+    sys.setswitchinterval(switch_interval)
+    try:
+        play()
+    finally:
+        sys.setswitchinterval(old_switch)
     with lock:
         for (k, rid), _ in pending.items():
             stats.failed.append((rid, "not finished before the time-out"))

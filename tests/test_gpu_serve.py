@@ -89,22 +89,23 @@ def test_tx_alone_equals_mix(ctx, precision):
     net.close()
 
 
-def test_feeder_alone_equals_mix(ctx):
+@pytest.mark.parametrize("sparse", [0, 1])
+def test_feeder_alone_equals_mix(ctx, sparse):
     from paper_2605_14103_amd import pf
-    say("serve feeder40")
+    say("serve feeder40, sparse update" if sparse else "serve feeder40")
     cfg = fdm.FeederConfig("feeder40", n_bus=40, max_depth=25, batch=1, seed=41)
     fd = fdm.make_feeder(cfg)
     net = pf.DistNetwork.from_feeder(ctx, fd)
     sizes = [3, 130, 1, 64, 200, 7, 129, 2]
     reqs = [fdm.make_batch(fd, cfg, batch=n, seed=500 + i) for i, n in enumerate(sizes)]
-    eng = pf.Engine(net, hbm_bytes=64 << 20, n_streams=2)
+    eng = pf.Engine(net, hbm_bytes=64 << 20, n_streams=2, zbus_sparse=sparse)
     say("engine", eng.info())
     for i, b in enumerate(reqs):
         eng.submit(i, b.s_wye, b.s_delta)
     got = _collect(eng, list(range(len(reqs))))
     say("after", eng.info())
     for i, b in enumerate(reqs):
-        v, it, ok = _alone_dist(net, b.s_wye, b.s_delta)
+        v, it, ok = _alone_dist(net, b.s_wye, b.s_delta, zbus_sparse=sparse)
         r = got[i]
         assert r.converged.all() and ok.all()
         assert np.array_equal(r.v.view(np.float64), v.view(np.float64)), f"request {i} differs from alone"
@@ -263,7 +264,7 @@ def test_full_size_networks_in_one_mix(ctx, precision):
         n.close()
 
 
-@pytest.mark.parametrize("kind", ["tx2000", "feeder300"])
+@pytest.mark.parametrize("kind", ["tx2000", "feeder300", "feeder300_sparse"])
 def test_caller_driven_steps(ctx, kind):
     """Caller-driven engine: scenarios admitted between steps into scattered
     free slots, one iteration per step, harvested as they finish and their
@@ -283,9 +284,9 @@ def test_caller_driven_steps(ctx, kind):
         net = pf.DistNetwork.from_feeder(ctx, fd)
         batch = fdm.make_batch(fd, fdm.FEEDER300, batch=24, seed=77)
         inputs = [batch.s_wye, batch.s_delta]
-        v_ref, it_ref, ok_ref = _alone_dist(net, *inputs)
+        v_ref, it_ref, ok_ref = _alone_dist(net, *inputs, zbus_sparse=int(kind.endswith("sparse")))
     assert ok_ref.all()
-    eng = pf.Engine(net, hbm_bytes=1 << 30, n_streams=0)
+    eng = pf.Engine(net, hbm_bytes=1 << 30, n_streams=0, zbus_sparse=int(kind.endswith("sparse")))
     slots_total = eng.info()["max_slots"]
     assert slots_total >= 16
     with pytest.raises(L.PfError) as e:      # caller-driven engines take no requests
