@@ -526,7 +526,7 @@ def bench_adjoint(steps: int, warmup: int) -> dict:
     return line
 
 
-def bench_serving(n_requests: int, lam: float, streams=(1, 2, 1), step_iters=(20, 1, 2), half: bool = True,
+def bench_serving(n_requests: int, lam: float, streams=(1, 3, 1), step_iters=(20, 1, 2), half: bool = True,
                   forcing: int = 0, feeder_sparse: int = 0) -> dict:
     """Replay the Poisson serving mix (30-bus grid, 2000-bus grid, 900-node feeder).
 
@@ -696,7 +696,7 @@ def main() -> int:
                              "tx2000_switch", "direct_sizes"])
     ap.add_argument("--requests", type=int, default=4000, help="serving: trace length")
     ap.add_argument("--lam", type=float, default=2000.0, help="serving: arrival rate (requests/s)")
-    ap.add_argument("--streams", default="1,2,1",
+    ap.add_argument("--streams", default="1,3,1",
                     help="serving: HIP streams of the 30-bus, 2000-bus and feeder engines")
     ap.add_argument("--step-iters", default="20,1,2",
                     help="serving: Newton updates / fixed-point iterations per engine step, per engine")

@@ -13,6 +13,7 @@ engine's own clock) fields, plus ``info()``.
 """
 from __future__ import annotations
 
+import gc
 import sys
 import threading
 import time
@@ -84,7 +85,7 @@ class ReplayStats:
 
 
 def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
-           timeout_s: float = 120.0, switch_interval: float = 2e-4) -> ReplayStats:
+           timeout_s: float = 120.0, switch_interval: float = 2e-4, pause_gc: bool = True) -> ReplayStats:
     """Play ``trace`` (requests with rid, t_arrive, network, n_scen) against ``engines``.
 
     ``inputs(req)`` returns the request's input arrays (host).  ``speed`` > 1
@@ -95,7 +96,10 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
     delays a submission.  While the trace plays, the interpreter's thread
     switch interval is ``switch_interval`` seconds (Python's default is 5
     ms, which a sleeping submitter could otherwise wait for while the
-    harvester runs Python code).
+    harvester runs Python code), and with ``pause_gc`` the cyclic garbage
+    collector is off (one collection before; a full collection in a large
+    process holds the interpreter for tens of milliseconds, which would
+    stall both threads and show up as latency of every engine).
     """
     order = sorted(trace, key=lambda r: r.t_arrive)
     pending: dict[tuple[int, int], tuple] = {}
@@ -105,6 +109,10 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
     staged = [(r, inputs(r)) for r in order]
     lock = threading.Lock()
     submitted_all = threading.Event()
+    gc_was = gc.isenabled()
+    if pause_gc:
+        gc.collect()
+        gc.disable()
     t0 = time.perf_counter()
 
     def harvest_once(wait: float) -> bool:
@@ -170,6 +178,8 @@ def replay(engines, trace, inputs, *, tol: float = 1e-8, speed: float = 1.0,
         play()
     finally:
         sys.setswitchinterval(old_switch)
+        if pause_gc and gc_was:
+            gc.enable()
     with lock:
         for (k, rid), _ in pending.items():
             stats.failed.append((rid, "not finished before the time-out"))
