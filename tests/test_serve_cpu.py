@@ -139,6 +139,30 @@ def test_replay_accounts_every_request(grids):
     assert set(summ["per_network"]) <= {0, 1}
 
 
+def test_replay_restores_interpreter_settings_and_splits_latency(grids):
+    """The replay pauses the garbage collector and shortens the thread switch
+    interval only while the trace plays; the summary's latency parts are the
+    submit lag, the queue and the service."""
+    import gc
+    import sys
+    cfg = wsv.ServingConfig(lam=400.0, n_requests=10, max_scen=3, n_networks=1, seed=4)
+    trace = wsv.make_trace(cfg)
+    eng = FakeEngine(grids[0], service=0.001)
+    switch, gc_on = sys.getswitchinterval(), gc.isenabled()
+    try:
+        st = serve.replay([eng], trace, _inputs(grids), timeout_s=30)
+    finally:
+        eng.close()
+    assert sys.getswitchinterval() == switch and gc.isenabled() == gc_on
+    parts = st.summary()["parts_ms"]
+    assert set(parts) == {"submit_lag", "queue", "service"}
+    for k, key in (("queue", "queue"), ("service", "service"), ("submit_lag", "submit_lag")):
+        vals = np.array([getattr(s, key) for s in st.served]) * 1e3
+        assert parts[k]["p50"] == pytest.approx(np.percentile(vals, 50))
+        assert parts[k]["p99"] == pytest.approx(np.percentile(vals, 99))
+    assert parts["service"]["p50"] >= 1.0 - 0.1
+
+
 def test_fifo_engine_queueing_shows_in_latency(grids):
     """A burst far above the fake engine's rate queues: later requests wait longer."""
     cfg = wsv.ServingConfig(lam=1e6, n_requests=12, max_scen=1, n_networks=1, seed=3)
