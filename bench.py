@@ -344,9 +344,9 @@ def bench_feeder(steps: int, warmup: int, cpu: dict | None) -> dict:
             "roofline": {"bound": "mfma", "achieved": tf, "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
                          "frac": tf / FP64_MFMA_TFLOPS,
                          "traffic": measured_traffic("zbus_feeder300_b4096.txt", "gemm_fp64", "zbus"),
-                         "traffic_unit": "HBM bytes per full zb_gemm<double> launch (rocprofv3 FETCH_SIZE + "
+                         "traffic_unit": "HBM bytes per full zb_gemm_direct<double> launch (rocprofv3 FETCH_SIZE + "
                                          "WRITE_SIZE, copy-calibrated)",
-                         "kernel": "zb_gemm<double>",
+                         "kernel": "zb_gemm_direct<double>",
                          "basis": "useful complex flops (8 nN^2 per scenario and iteration) over the whole "
                                   "solve time, residual kernels and launch gaps included"},
             "fp64": runs["fp64"], "mixed": runs["mixed"],

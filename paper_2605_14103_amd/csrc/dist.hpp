@@ -66,7 +66,9 @@ struct DistNetwork {
   int zf_nfq = 0, zf_nbq = 0;
   DeviceBuffer zf_pinv, zf_fmeta, zf_frow, zf_fcol, zf_bmeta, zf_brow, zf_bcol;
   DeviceBuffer zf_fval64, zf_bval64, zf_bd64, zf_fval32, zf_bval32, zf_bd32;
-  DeviceBuffer W64, W32;   // Kp x Np real-block Z (Np = 2 nN rounded up to the N tile)
+  DeviceBuffer W64, W32;   // Kp x Np real-block Z (Np = 2 nN rounded up to the N tile); W32
+                           // row-major, W64 in K blocks of ZB_BK: (k, n) at
+                           // ((k / ZB_BK) Np + n) ZB_BK + k % ZB_BK
   DeviceBuffer slack_d;    // 3 slack node indices
   DeviceBuffer vslack_d;   // 6 doubles
   // workspaces (grow-only); calls on one network must not overlap

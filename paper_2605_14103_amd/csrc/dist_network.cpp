@@ -206,6 +206,7 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
     v0[2 * i + 1] = -s.imag();
   }
   const int Kp = net->Kp, Np = net->Np;
+  // W row-major (Kp x Np; the FP32 copy keeps this layout) ...
   std::vector<double> W((size_t)Kp * Np, 0.0);
   for (int i = 0; i < nN; ++i)
     for (int l = 0; l < nN; ++l) {
@@ -215,6 +216,10 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
       W[(size_t)(2 * l) * Np + 2 * i + 1] = z.imag();
       W[(size_t)(2 * l + 1) * Np + 2 * i + 1] = z.real();
     }
+  // ... and the FP64 copy in K blocks of ZB_BK: (k, n) at ((k / ZB_BK) Np + n) ZB_BK + k % ZB_BK
+  std::vector<double> Wb((size_t)Kp * Np);
+  for (int k = 0; k < Kp; ++k)
+    for (int n = 0; n < Np; ++n) Wb[((size_t)(k / ZB_BK) * Np + n) * ZB_BK + k % ZB_BK] = W[(size_t)k * Np + n];
 
   // Load tables.
   std::vector<uint8_t> wye(nN, 0);
@@ -334,7 +339,7 @@ DistNetwork* dist_network_create(Context* ctx, int n_node, int nnz, const int32_
   net->c = upload(ctx, cc);
   net->v0 = upload(ctx, v0);
   net->free2ext_d = upload(ctx, net->free2ext);
-  net->W64 = upload(ctx, W);
+  net->W64 = upload(ctx, Wb);
   net->W32 = upload(ctx, std::vector<float>(W.begin(), W.end()));
   net->slack_d = upload(ctx, std::vector<int>(net->slack, net->slack + 3));
   net->vslack_d = upload(ctx, std::vector<double>(net->v_slack, net->v_slack + 6));

@@ -12,9 +12,10 @@
 //   zb_residual   one workgroup per scenario: wye and delta load currents,
 //                 sparse Y_NN v (sliced ELLPACK, v staged in LDS), r,
 //                 max |v * conj(r)|, flags, sum |v|
-//   zb_gemm       D = R W (real-block form of Z r) on MFMA 16x16x4 tiles, with
-//                 the FP64 update v += D fused into the epilogue
-//   zb_sparse     (sparse variant, instead of zb_gemm) v += Y_NN^-1 r by
+//   zb_gemm_*     D = R W (real-block form of Z r) on MFMA 16x16x4 tiles, with
+//                 the FP64 update v += D fused into the epilogue (FP64:
+//                 operands straight from memory; FP32: staged through LDS)
+//   zb_sparse     (sparse variant, instead of the GEMM) v += Y_NN^-1 r by
 //                 level-scheduled solves with the sparse L D L^T of Y_NN
 #include <hip/hip_runtime.h>
 
@@ -243,9 +244,10 @@ struct Mfma<float> {
   static __device__ __forceinline__ int out_row(int lane, int v) { return 4 * (lane / 16) + v; }
 };
 
-// D = R W on a ZB_BM x ZB_BN tile per workgroup (4 waves, 2 x 2, 64 x 64 each,
-// 4 x 4 MFMA 16x16x4 tiles per wave), K in steps of ZB_BK staged through LDS,
-// double buffered.  Epilogue: v += D for active scenarios (FP64).
+// FP32 form (mixed precision): D = R W on a ZB_BM x ZB_BN tile per
+// workgroup (4 waves, 2 x 2, 64 x 64 each, 4 x 4 MFMA 16x16x4 tiles per
+// wave), K in steps of ZB_BK staged through LDS, double buffered; W row-major
+// (Kp x Np).  Epilogue: v += D for active scenarios (FP64).
 //
 // LDS rows are padded by 16 elements so that the four row groups a fragment
 // read touches (one per 16 lanes) start in different banks.  Two workgroups
@@ -255,7 +257,7 @@ struct Mfma<float> {
 constexpr int ZB_PAD = 16;
 
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zb_gemm(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zb_gemm_lds(
     DistDev net, const T* __restrict__ W, ZbusLaunch a, int it) {
   using V4 = typename Mfma<T>::V4;
   const int Kp = net.Kp, Np = net.Np;
@@ -340,6 +342,118 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
     step(kt, std::integral_constant<int, 0>{});
     if (kt + 1 < nk) step(kt + 1, std::integral_constant<int, 1>{});
   }
+  const int ncol = 2 * net.nN;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) {
+      const int row = row0 + wm * 64 + i * 16 + Mfma<T>::out_row(lane, vv);
+      if (row >= a.batch) continue;
+      const int sc = zb_slot(a, row);
+      if (a.active[sc] == 0) continue;
+      double* vrow = a.v + (int64_t)sc * Kp;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = col0 + wn * 64 + j * 16 + (lane & 15);
+        if (col < ncol) vrow[col] += (double)acc[i][j][vv];
+      }
+    }
+  }
+}
+
+// FP64 form: D = R W on a ZB_BM x ZB_BN tile per workgroup (4 waves, 2 x 2,
+// 64 x 64 each, 4 x 4 MFMA 16x16x4 tiles per wave).  Epilogue: v += D for
+// active scenarios.
+//
+// No LDS and no barrier in the K loop: each wave loads its own operands
+// straight into registers in the MFMA's lane layout.  The sum over a K block
+// of 16 may visit k in any order as long as A and B agree, so in the block's
+// MFMA number c (0..3) lane group g = lane / 16 supplies k = 4 g + c: a
+// lane's four k values are contiguous in R's row, and W is stored in K
+// blocks of 16 (element (k, n) at ((k / 16) Np + n) 16 + k % 16) so that
+// they are contiguous there too.  Operands arrive in 16-byte loads of CH
+// values (a substep: CH MFMAs per tile pair), one substep ahead in a second
+// register set.  Two workgroups per CU (two waves per SIMD): the 4 x 4
+// accumulator tiles and the two operand sets fit in half the register file.
+// (In FP32 a lane's four k values take half a 128-byte line, and the eight
+// waves of a CU touch more lines than L1 holds before each line's second
+// half is read: the FP32 form keeps the LDS kernel above, which measured
+// 275 us against about 440 us for this one at batch 4096.)
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void zb_gemm_direct(
+    DistDev net, const T* __restrict__ W, ZbusLaunch a, int it) {
+  using V4 = typename Mfma<T>::V4;
+  constexpr int CH = 16 / sizeof(T);   // values per 16-byte load
+  constexpr int NS = ZB_BK / 4 / CH;   // substeps per K block
+  typedef T VC __attribute__((ext_vector_type(CH)));
+  typedef __attribute__((address_space(1))) const VC GVC;
+  const int Kp = net.Kp, Np = net.Np;
+  // Workgroups are dealt to the 8 XCDs round robin (workgroup id mod 8).  When
+  // the tile count divides by 8, XCD x gets the contiguous tile range
+  // [x T/8, (x+1) T/8) in row-major tile order, so the R rows of a tile row
+  // are read into one XCD's L2 and W streams through each L2 once.
+  const int nt = Np / ZB_BN, ntiles = gridDim.x;
+  const int id = blockIdx.x;
+  const int lin = (ntiles & 7) == 0 ? (id & 7) * (ntiles >> 3) + (id >> 3) : id;
+  const int tile_n = lin % nt, tile_m = lin / nt;
+  const int row0 = tile_m * ZB_BM, col0 = tile_n * ZB_BN;
+  const int t = threadIdx.x;
+  if (a.count && a.count[it] == 0) return;  // no scenario left active (uniform)
+  {
+    int act = 0;
+    if (t < ZB_BM && row0 + t < a.batch) act = a.active[zb_slot(a, row0 + t)];
+    if (!__syncthreads_or(act)) return;
+  }
+  const T* R = reinterpret_cast<const T*>(a.r);
+  const int lane = t & (WAVE - 1), wave = t / WAVE;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int g = lane >> 4, r = lane & 15;
+  // this lane's operand rows: R row (tile row i) and W column (tile column j)
+  const T* Ab = R + (int64_t)(row0 + wm * 64 + r) * Kp + 4 * g;
+  const T* Bb = W + (int64_t)(col0 + wn * 64 + r) * ZB_BK + 4 * g;
+  const int64_t a_i = (int64_t)16 * Kp, b_j = 16 * ZB_BK, b_kb = (int64_t)Np * ZB_BK;
+
+  V4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = V4{0, 0, 0, 0};
+
+  VC ao[2][4], bo[2][4];
+  auto load = [&](int u, int set) {  // substep u: K block u / NS, part u % NS
+    const int kb = u / NS, q = (u % NS) * CH;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ao[set][i] = *(GVC*)(Ab + i * a_i + kb * ZB_BK + q);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bo[set][j] = *(GVC*)(Bb + j * b_j + kb * b_kb + q);
+  };
+  auto compute = [&](int set) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::op(ao[set][i][c], bo[set][j][c], acc[i][j]);
+  };
+  // Straight-line pairs of substeps; past the last substep the loads repeat
+  // it (into a set nothing reads again).  The scheduling barriers keep each
+  // substep's loads ahead of the previous substep's products (left alone,
+  // the compiler gathers a pair's loads at the top of the pair, so each
+  // product waits for a load issued just before it).
+  const int nu = Kp / ZB_BK * NS;
+  load(0, 0);
+  int u = 0;
+  for (; u + 2 <= nu; u += 2) {
+    load(u + 1, 1);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(min(u + 2, nu - 1), 0);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (u < nu) compute(0);
   const int ncol = 2 * net.nN;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -491,6 +605,15 @@ __global__ __launch_bounds__(ZB_THREADS) void zb_finish(DistDev net, ZbusLaunch 
   }
 }
 
+// The update's GEMM: FP64 without LDS (W in K blocks), FP32 through LDS (W row-major).
+template <typename T>
+void launch_gemm(const DistDev& d, const T* W, const ZbusLaunch& a, int it, int tiles, hipStream_t s) {
+  if constexpr (sizeof(T) == 8)
+    hipLaunchKernelGGL(zb_gemm_direct<T>, dim3(tiles), dim3(256), 0, s, d, W, a, it);
+  else
+    hipLaunchKernelGGL(zb_gemm_lds<T>, dim3(tiles), dim3(256), 0, s, d, W, a, it);
+}
+
 template <typename T>
 void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
   const DistDev d = net.view();
@@ -511,7 +634,7 @@ void run_zbus_t(DistNetwork& net, const ZbusLaunch& a, hipStream_t s) {
     if (a.sparse) {
       hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a, it);
     } else {
-      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a, it);
+      launch_gemm<T>(d, W, a, it, nt * mt, s);
     }
     PFX_HIP(hipGetLastError());
   };
@@ -576,7 +699,7 @@ void zbus_step_t(DistNetwork& net, const ZbusLaunch& a, int iters, hipStream_t s
     if (a.sparse) {
       hipLaunchKernelGGL(zb_sparse<T>, dim3(B), dim3(WAVE), (size_t)d.nN * 2 * sizeof(T), s, d, a, 0);
     } else {
-      hipLaunchKernelGGL(zb_gemm<T>, dim3(nt * mt), dim3(256), 0, s, d, W, a, 0);
+      launch_gemm<T>(d, W, a, 0, nt * mt, s);
     }
     PFX_HIP(hipGetLastError());
   }
